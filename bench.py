@@ -1,0 +1,180 @@
+"""Benchmark of the assembled SEM screened-Poisson operator and CG on one MI355X.
+
+Workload: 32^3 affine hexahedra at N=7 (11,390,625 assembled DOFs, 16.8M local
+nodes, 7 FP64 geometric factors per node), lambda = 1, seeded U[-1,1) forcing.
+One step = the paper's operator protocol (50 back-to-back operator calls) plus
+one 100-iteration CG solve (the benchmark's fixed iteration count), all inputs
+resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+AX_CALLS = 50
+CG_ITERS = 100
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ax_f64_box32_N7_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_12477_amd", "csrc", f) for f in ("ax_impl.h", "reduce.h", "common.h")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per operator launch from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken from a different kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def stream_rate(hb, torch, n=1 << 25, reps=10):
+    """Measured 8:1 streaming rate (GB/s), median of reps."""
+    inp = torch.ones(8 * n, dtype=torch.float64, device="cuda")
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    hb.stream_probe(inp, out)
+    times = []
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        hb.stream_probe(inp, out)
+        e.record()
+        e.synchronize()
+        times.append(s.elapsed_time(e) * 1e-3)
+    del inp, out
+    return 9 * 8 * n / statistics.median(times) / 1e9
+
+
+def cpu_baseline(case, reps=8):
+    """The oracle (plain C, single thread) timed on a bounded sample of the same workload."""
+    import oracle
+
+    m = oracle.Mesh(case.nx, case.ny, case.nz, case.N, jitter=case.jitter, seed=case.mesh_seed)
+    b = oracle.rhs(m.NG, case.rhs_seed)
+    m.ax(b, case.lam)  # warm
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m.ax(b, case.lam)
+    dt = time.perf_counter() - t0
+    return {"value": m.NG * reps / dt / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} operator applications y = A x on the same {case.nx}^3 N={case.N} mesh "
+                      f"({m.NG} DOFs), one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the operator and CG of this library run on a single device "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import inputs
+    import paper_2202_12477_amd as hb
+    from paper_2202_12477_amd import metrics
+
+    case = inputs.PLAIN_LARGE
+    torch.cuda.set_device(0)
+    B = stream_rate(hb, torch)
+    m = hb.Mesh(case.nx, case.ny, case.nz, case.N, jitter=case.jitter, seed=case.mesh_seed)
+    NG, NL, E = m.NG, m.NL, m.E
+    b = torch.empty(NG, dtype=torch.float64, device="cuda")
+    hb.rhs_uniform(b, case.rhs_seed)
+    y = torch.empty_like(b)
+    yk = torch.zeros_like(b)
+    x = torch.empty_like(b)
+
+    def step(ev):
+        ev[0].record()
+        for _ in range(AX_CALLS):
+            m.ax(case.lam, b, y)
+        ev[1].record()
+        for _ in range(AX_CALLS):
+            m.ax_add(case.lam, b, yk)
+        ev[2].record()
+        res = m.cg(case.lam, b, x, max_iter=CG_ITERS, fixed_iters=True, history=False)
+        ev[3].record()
+        assert res.iters == CG_ITERS and res.status == hb.HB_OK, res
+
+    for _ in range(args.warmup):
+        step([torch.cuda.Event(enable_timing=True) for _ in range(4)])
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        step(ev)
+        evs.append(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_ax = sum(e[0].elapsed_time(e[1]) for e in evs) * 1e-3
+    t_kern = sum(e[1].elapsed_time(e[2]) for e in evs) * 1e-3
+    t_cg = sum(e[2].elapsed_time(e[3]) for e in evs) * 1e-3
+    t_step = sum(e[0].elapsed_time(e[3]) for e in evs) * 1e-3
+
+    ax_gdofs = NG * AX_CALLS * args.steps / t_ax / 1e9
+    kern_s = t_kern / (AX_CALLS * args.steps)
+    ax_bytes = metrics.ax_bytes_fused(NG, NL)
+    achieved = ax_bytes / kern_s / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "Ax GDOF/s",
+        "value": round(ax_gdofs, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "box32_N7_affine: 32^3 hex elements, N=7, 11,390,625 DOFs, lambda=1, "
+                               "U[-1,1) forcing; step = 50 operator calls + 100 CG iterations",
+                   "E": E, "N": case.N, "n_global": NG, "n_local": NL},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": f"ax_kernel<{case.N},false>", "kernel_us": round(kern_s * 1e6, 2),
+                     "algorithmic_bytes": int(ax_bytes)},
+        "ax_gdofs_kernel_only": round(NG / kern_s / 1e9, 3),
+        "ax_gflops": round(metrics.ax_flops(E, case.N) / kern_s / 1e9, 1),
+        "cg_gdofs": round(NG * CG_ITERS * args.steps / t_cg / 1e9, 3),
+        "cg_ms_per_iter": round(t_cg / (CG_ITERS * args.steps) * 1e3, 4),
+        "cg_fom_gflops_nekbone": round(metrics.fom(E, case.N, CG_ITERS * args.steps, t_cg) / 1e9, 1),
+        "stream_8to1_gbs": round(B, 1),
+        "frac_of_stream": round(achieved / B, 4),
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,167 @@
+/*
+ * hbmi.h -- C ABI of an MI355X-native assembled spectral-element screened
+ * Poisson operator and the conjugate-gradient solve around it.
+ *
+ * The method is hipBone's (Chalmers, Karakus, Austin, Swirydowicz &
+ * Warburton, arXiv:2202.12477): a box mesh of E hexahedra of degree N,
+ * the screened Poisson operator A = S + lambda*(mass) of eq. (poisson), with the
+ * stiffness S = Z^T S_L Z of eq. (stiffness), S_L^e = D^T G^e D, applied
+ * matrix-free to an *assembled* DOF vector (DOF Storage section), inside
+ * Algorithm 1 (unpreconditioned CG) with fused vector kernels (Conjugate
+ * gradient Iteration section).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns hb_status and never throws.  On failure a
+ *    thread-local message is available from hb_last_error().
+ *  - "dev_" pointers are device (HBM) pointers of the current HIP device,
+ *    8-byte aligned, not aliasing each other; the caller owns them.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; functions that return host results synchronise it.
+ *  - Assembled vectors have N_G = (nx*N+1)(ny*N+1)(nz*N+1) entries in
+ *    lexicographic global order g = I + gx*(J + gy*K), gx = nx*N+1,
+ *    gy = ny*N+1, where global node (I,J,K) = (ex*N+a, ey*N+b, ez*N+c) for local
+ *    GLL node (a,b,c) of element (ex,ey,ez).  No boundary node is masked.
+ *  - A mesh object is not thread-safe: calls on one mesh from several host
+ *    threads, or on several streams at once, must be serialised by the caller
+ *    (the CG workspace is owned by the mesh).
+ */
+#ifndef HBMI_H
+#define HBMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HB_OK = 0,
+    HB_ERR_INVALID_ARG = 1,   /* null pointer, N outside 1..15, n < 1, lambda <= 0, jitter outside [0,0.5), ... */
+    HB_ERR_OUT_OF_MEMORY = 2, /* device allocation failed */
+    HB_ERR_DEVICE = 3,        /* no HIP device, or a HIP runtime error (message in hb_last_error) */
+    HB_ERR_NOT_CONVERGED = 4, /* tolerance not met within max_iter (results are still filled) */
+    HB_ERR_BREAKDOWN = 5,     /* p.Ap <= 0 or not finite during CG */
+    HB_ERR_NONFINITE = 6,     /* the initial residual r0.r0 is NaN or Inf */
+    HB_ERR_BUDGET = 7,        /* reserved: request larger than a memory budget */
+    HB_ERR_BUSY = 8           /* reserved */
+} hb_status;
+
+/* Mass coefficient c of the lambda term (7th geometric value per node).
+ * HB_MASS_GWJ: c = w_a w_b w_c J (GLL weight times Jacobian): A = S + lambda*M.
+ * HB_MASS_INVDEG: c = 1/multiplicity of the node's global DOF, the inverse
+ * degree weights W of the Poisson Operator section (Z^T W Z = I), giving
+ * A = S + lambda*I exactly as eq. (poisson) writes it. */
+typedef enum { HB_MASS_GWJ = 0, HB_MASS_INVDEG = 1 } hb_mass;
+
+typedef struct hb_mesh_s *hb_mesh;
+
+/* Box mesh on [0,1]^3 (NekBone section: a regular mesh of E hexahedra with
+ * (N+1)^3 GLL nodes each).  Trilinear elements: vertices strictly inside the
+ * box are moved by h_d*jitter*(2U-1) per coordinate d, U uniform in [0,1) from
+ * the splitmix64 stream d+1 of `seed` at the vertex's lexicographic index
+ * i + (nx+1)(j + (ny+1)k) (the same counter-based generator as hb_rhs_uniform). */
+typedef struct {
+    int32_t nx, ny, nz; /* elements per direction, >= 1 */
+    int32_t N;          /* polynomial degree, 1..15 */
+    double jitter;      /* 0 <= jitter < 0.5 (0: affine box) */
+    uint64_t seed;      /* jitter seed */
+    int32_t mass;       /* hb_mass */
+    int32_t reserved;   /* must be 0 */
+} hb_mesh_desc;
+
+typedef struct {
+    int64_t n_elem;       /* E */
+    int64_t n_local;      /* N_L = E (N+1)^3 */
+    int64_t n_global;     /* N_G */
+    int32_t N;
+    int32_t reserved;
+    size_t device_bytes;  /* device memory currently held by the mesh (geometry, map, D, CG workspace) */
+} hb_mesh_info;
+
+/* Build the mesh on the device: GLL nodes/weights and the 1D derivative
+ * matrix D (NekBone section), the scatter map Z as int32 [E][(N+1)^3], and the
+ * geometric factors G_rr, G_rs, G_rt, G_ss, G_st, G_tt and c as FP64
+ * [E][7][(N+1)^3] (G_dd' = w_a w_b w_c J sum_i dxi_d/dx_i dxi_d'/dx_i, the
+ * metric tensor combined with the GLL weights).  Synchronises `stream`.
+ * Errors: HB_ERR_INVALID_ARG (bad desc, N_G or N_L >= 2^31, non-positive
+ * Jacobian), HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE.  *out is NULL on failure. */
+hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out);
+
+/* Release every device buffer of the mesh.  NULL is accepted (no-op). */
+hb_status hb_mesh_destroy(hb_mesh mesh);
+
+hb_status hb_mesh_query(hb_mesh mesh, hb_mesh_info *info);
+
+/* Copy mesh data to host memory (any pointer may be NULL to skip it):
+ * host_geo: 7*N_L doubles, layout [E][7][(N+1)^3]; host_map: N_L int32;
+ * host_D: (N+1)^2 doubles row-major, D[i][j] = l_j'(xi_i);
+ * host_xi, host_w: N+1 doubles each (GLL nodes ascending, weights).
+ * Synchronous. */
+hb_status hb_mesh_export(hb_mesh mesh, double *host_geo, int32_t *host_map, double *host_D, double *host_xi,
+                         double *host_w);
+
+/* Forcing vector (HipBone section: filled once by a pseudo-random kernel):
+ * dev_b[g] = 2U - 1 in [-1,1), U from splitmix64 (Steele, Lea & Flood 2014)
+ * stream 0 of `seed`: the stream starts at output number 0 of the sequence
+ * started at `seed`; U is the top 53 bits of that stream's output number g,
+ * times 2^-53.  Asynchronous.  n >= 0. */
+hb_status hb_rhs_uniform(int64_t n, uint64_t seed, double *dev_b, void *stream);
+
+/* y = A x (eq. poisson / eq. stiffness, fused): gather x through Z, apply
+ * D (r,s,t), the 6 symmetric G factors and lambda*c, apply D^T, and assemble
+ * with Z^T into y.  x and y are FP64 device vectors of N_G entries and must not
+ * overlap.  y is overwritten.  lambda > 0 (with no masked boundary S has
+ * the constants in its null space, so lambda = 0 makes A singular).
+ * Asynchronous; assembly uses device atomics, so results may differ between
+ * calls in the last bits (summation order).  Not thread-safe per mesh. */
+hb_status hb_ax(hb_mesh mesh, double lambda, const double *dev_x, double *dev_y, void *stream);
+
+/* y += A x: the same fused operator, assembling into y without clearing it
+ * first (hb_ax = clear y, then this).  Same arguments and rules as hb_ax. */
+hb_status hb_ax_add(hb_mesh mesh, double lambda, const double *dev_x, double *dev_y, void *stream);
+
+/* Options of hb_cg_solve (Algorithm 1). */
+typedef struct {
+    int32_t max_iter;    /* iteration cap (>= 0); in fixed mode the exact count */
+    int32_t fixed_iters; /* 1: run exactly max_iter iterations (the benchmark's 100); 0: stop on rtol */
+    double rtol;         /* stop once ||r_j||_2 <= rtol ||b||_2 (recursive residual) */
+    int32_t x0_zero;     /* 1: ignore dev_x on entry and start from x0 = 0 (r0 = b, no operator call) */
+    int32_t check_every; /* tolerance mode: read the device state back every this many iterations (<=0: 25) */
+} hb_cg_opts;
+
+typedef struct {
+    int32_t iters;       /* iterations completed */
+    int32_t status;      /* hb_status of the solve */
+    double res0;         /* ||r_0|| */
+    double res;          /* ||r_iters|| (recursive) */
+    double bnorm;        /* ||b|| */
+} hb_cg_result;
+
+/* Algorithm 1 on the assembled system A x = b: r0 = b - A x0, p = r0; per
+ * iteration Ap = A p (with p.Ap fused into the operator), alpha = r.r / p.Ap,
+ * x += alpha p, r -= alpha Ap fused with r.r, beta = r'.r' / r.r, p = r + beta p.
+ * All scalars stay on the device; dot products are two-stage FP64 reductions
+ * with a fixed final order.  Stops early (status) on p.Ap <= 0 (BREAKDOWN),
+ * a non-finite r0.r0 (NONFINITE) or r.r == 0 (exact solution, OK).
+ * dev_b: N_G doubles; dev_x: N_G doubles, initial guess in, solution out.
+ * host_res_hist: NULL or room for max_iter+1 doubles, receives ||r_j||, j = 0..iters.
+ * Synchronises `stream` before returning.  Returns the solve's status
+ * (HB_OK, HB_ERR_NOT_CONVERGED, HB_ERR_BREAKDOWN, HB_ERR_NONFINITE) or an
+ * argument/device error. */
+hb_status hb_cg_solve(hb_mesh mesh, double lambda, const double *dev_b, double *dev_x, const hb_cg_opts *opts,
+                      hb_cg_result *result, double *host_res_hist, void *stream);
+
+/* Empirical streaming probe of the Computational Tests section: every thread
+ * reads 8 FP64 values and writes one (8:1 read:write), dev_out[i] =
+ * sum_k dev_in[k*n + i], k = 0..7.  dev_in: 8n doubles, dev_out: n doubles.
+ * Asynchronous. */
+hb_status hb_stream_probe(const double *dev_in, double *dev_out, int64_t n, void *stream);
+
+const char *hb_status_string(hb_status status);
+const char *hb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HBMI_H */

@@ -1,0 +1,247 @@
+"""Python binding of libhbmi (include/hbmi.h): argument marshalling only.
+
+Every step of the computation runs in the HIP library; this module converts
+torch device tensors into device pointers and the current HIP stream into a
+stream handle, and turns status codes into exceptions.  If libhbmi.so has not
+been built the import still succeeds, but the first call raises: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhbmi.so")
+
+HB_OK = 0
+HB_ERR_INVALID_ARG = 1
+HB_ERR_OUT_OF_MEMORY = 2
+HB_ERR_DEVICE = 3
+HB_ERR_NOT_CONVERGED = 4
+HB_ERR_BREAKDOWN = 5
+HB_ERR_NONFINITE = 6
+HB_ERR_BUDGET = 7
+HB_ERR_BUSY = 8
+
+MASS_GWJ = 0
+MASS_INVDEG = 1
+
+# Every entry point of include/hbmi.h, in declaration order.
+EXPORTS = (
+    "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax",
+    "hb_ax_add", "hb_cg_solve", "hb_stream_probe", "hb_status_string", "hb_last_error",
+)
+
+
+class HbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_status_name(status)}: {msg}")
+        self.status = status
+
+
+class _MeshDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("jitter", ctypes.c_double), ("seed", ctypes.c_uint64), ("mass", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _MeshInfo(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int64), ("n_local", ctypes.c_int64), ("n_global", ctypes.c_int64),
+                ("N", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+
+
+class _CgOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class _CgResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("res0", ctypes.c_double),
+                ("res", ctypes.c_double), ("bnorm", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhbmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2202_12477_amd.build` "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "hb_mesh_create": [ctypes.POINTER(_MeshDesc), vp, ctypes.POINTER(vp)],
+        "hb_mesh_destroy": [vp],
+        "hb_mesh_query": [vp, ctypes.POINTER(_MeshInfo)],
+        "hb_mesh_export": [vp, vp, vp, vp, vp, vp],
+        "hb_rhs_uniform": [i64, u64, vp, vp],
+        "hb_ax": [vp, f64, vp, vp, vp],
+        "hb_ax_add": [vp, f64, vp, vp, vp],
+        "hb_cg_solve": [vp, f64, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp, vp],
+        "hb_stream_probe": [vp, vp, i64, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = i32
+    L.hb_status_string.argtypes = [i32]
+    L.hb_status_string.restype = ctypes.c_char_p
+    L.hb_last_error.argtypes = []
+    L.hb_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _status_name(st: int) -> str:
+    try:
+        return lib().hb_status_string(st).decode()
+    except Exception:  # library missing: still give a readable name
+        return f"status {st}"
+
+
+def _check(st: int, what: str, ok=(HB_OK,)):
+    if st not in ok:
+        raise HbError(st, f"{what}: {lib().hb_last_error().decode()}")
+    return st
+
+
+def _stream(stream) -> int | None:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t, dtype=None) -> int:
+    import torch
+
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+@dataclass
+class CgResult:
+    iters: int
+    status: int
+    res0: float
+    res: float
+    bnorm: float
+    history: "list[float] | None" = None
+
+
+class Mesh:
+    """A device-resident box mesh (hb_mesh_create / hb_mesh_destroy)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, N: int, jitter: float = 0.0, seed: int = 0,
+                 mass: int = MASS_GWJ, stream=None):
+        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, 0)
+        h = ctypes.c_void_p()
+        _check(lib().hb_mesh_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)), "hb_mesh_create")
+        self._h = h
+        info = _MeshInfo()
+        _check(lib().hb_mesh_query(h, ctypes.byref(info)), "hb_mesh_query")
+        self.nx, self.ny, self.nz, self.N = nx, ny, nz, N
+        self.E, self.NL, self.NG = info.n_elem, info.n_local, info.n_global
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("mesh destroyed")
+        return self._h
+
+    def device_bytes(self) -> int:
+        info = _MeshInfo()
+        _check(lib().hb_mesh_query(self.handle, ctypes.byref(info)), "hb_mesh_query")
+        return int(info.device_bytes)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().hb_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def export(self):
+        """Host copies: (geo [E,7,Np] float64, map [E,Np] int32, D, xi, w) as numpy arrays."""
+        import numpy as np
+
+        n1 = self.N + 1
+        geo = np.empty((self.E, 7, n1 ** 3))
+        mp = np.empty((self.E, n1 ** 3), dtype=np.int32)
+        D, xi, w = np.empty((n1, n1)), np.empty(n1), np.empty(n1)
+        _check(lib().hb_mesh_export(self.handle, geo.ctypes.data, mp.ctypes.data, D.ctypes.data, xi.ctypes.data,
+                                    w.ctypes.data), "hb_mesh_export")
+        return geo, mp, D, xi, w
+
+    def ax(self, lam: float, x, y, stream=None):
+        """y = A x on the device (asynchronous on the stream)."""
+        import torch
+
+        if x.numel() != self.NG or y.numel() != self.NG:
+            raise ValueError("vectors must have N_G entries")
+        _check(lib().hb_ax(self.handle, lam, _ptr(x, torch.float64), _ptr(y, torch.float64), _stream(stream)), "hb_ax")
+        return y
+
+    def ax_add(self, lam: float, x, y, stream=None):
+        """y += A x on the device (asynchronous on the stream)."""
+        import torch
+
+        if x.numel() != self.NG or y.numel() != self.NG:
+            raise ValueError("vectors must have N_G entries")
+        _check(lib().hb_ax_add(self.handle, lam, _ptr(x, torch.float64), _ptr(y, torch.float64), _stream(stream)),
+               "hb_ax_add")
+        return y
+
+    def cg(self, lam: float, b, x, *, max_iter: int = 100, fixed_iters: bool = True, rtol: float = 0.0,
+           x0_zero: bool = True, check_every: int = 0, history: bool = True, stream=None,
+           raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)) -> CgResult:
+        """Algorithm 1 on the device; x holds the initial guess (unless x0_zero) and the result."""
+        import torch
+
+        if b.numel() != self.NG or x.numel() != self.NG:
+            raise ValueError("vectors must have N_G entries")
+        opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every)
+        res = _CgResult()
+        hist = (ctypes.c_double * (max_iter + 1))() if history else None
+        st = lib().hb_cg_solve(self.handle, lam, _ptr(b, torch.float64), _ptr(x, torch.float64), ctypes.byref(opts),
+                               ctypes.byref(res), hist, _stream(stream))
+        if st in raise_on:
+            _check(st, "hb_cg_solve")
+        out = CgResult(res.iters, res.status, res.res0, res.res, res.bnorm)
+        if history:
+            out.history = list(hist[: res.iters + 1])
+        return out
+
+
+def rhs_uniform(b, seed: int, stream=None):
+    """Fill a float64 device vector with the seeded U[-1,1) forcing."""
+    import torch
+
+    _check(lib().hb_rhs_uniform(b.numel(), seed, _ptr(b, torch.float64), _stream(stream)), "hb_rhs_uniform")
+    return b
+
+
+def stream_probe(inp, out, stream=None):
+    """8:1 streaming probe: out[i] = sum_k inp[k*n + i]."""
+    import torch
+
+    n = out.numel()
+    if inp.numel() != 8 * n:
+        raise ValueError("inp must hold 8*n entries")
+    _check(lib().hb_stream_probe(_ptr(inp, torch.float64), _ptr(out, torch.float64), n, _stream(stream)),
+           "hb_stream_probe")
+    return out

@@ -1,0 +1,187 @@
+// The fused assembled screened-Poisson operator y = Z^T (S_L + lambda C) Z x
+// (eq. poisson and eq. stiffness; the fused gather of the Poisson Operator
+// section, with the Z^T assembly fused as well).
+//
+// Work decomposition (gfx950, wave64): a thread owns one (a,b) column of one
+// element and walks its N+1 nodes along t, so
+//   - the t-derivative and the t-part of D^T are register-only;
+//   - the r/s derivatives of layer c read one (N+1)^2 slice from LDS, and the
+//     r/s parts of D^T read one slice of f_r, f_s;
+//   - the rows/columns of D a thread needs live in registers (reused by every
+//     layer); D[c][*] is uniform across the block and comes through the
+//     scalar cache;
+//   - each block holds EPB elements (EPB*(N+1)^2 <= 256 threads), so N=7 is
+//     one wave per element and low orders pack several elements per wave.
+// HBM streams: map (4 B/node) and the 7 geometric values (56 B/node) once,
+// coalesced per layer; x through an indirect (cache-friendly) gather; y by
+// device-scope FP64 atomic adds into a zeroed vector.
+#pragma once
+
+#include "common.h"
+#include "reduce.h"
+
+namespace hb {
+
+template <int N>
+struct AxShape {
+    static constexpr int n1 = N + 1;
+    static constexpr int np2 = n1 * n1;
+    static constexpr int np3 = np2 * n1;
+    static constexpr int epb = (256 / np2) > 0 ? (256 / np2) : 1;
+    static constexpr int threads = (epb * np2 + 63) / 64 * 64;
+    // Registers per thread: 4(N+1) doubles of D (rows and columns a, b), the
+    // t-column of x, f_t and y (3(N+1) doubles), the map column (N+1) and a
+    // layer of G: about 15(N+1)+40 VGPRs.  Ask for the occupancy that fits it,
+    // so the compiler neither spills nor hoists every layer's loads at once.
+    static constexpr int vgprs = (15 * n1 + 40 + 7) / 8 * 8;
+    static constexpr int waves_per_eu = 512 / vgprs < 1 ? 1 : (512 / vgprs > 8 ? 8 : 512 / vgprs);
+};
+
+// Materialise a value here: stops the compiler from sinking a layer's
+// arithmetic to the end of the kernel, which would keep every layer's LDS
+// operands live at once.
+__device__ inline void pin(double &v) { asm volatile("" : "+v"(v)); }
+
+__device__ inline void atomic_add_f64(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int N, bool DOT>
+__global__ __launch_bounds__(AxShape<N>::threads)
+void ax_kernel(
+    int64_t E, const int32_t *__restrict__ map, const double *__restrict__ geo, const double *__restrict__ Dm,
+    double lambda, const double *__restrict__ x, double *__restrict__ y, double *__restrict__ partial,
+    const CgState *__restrict__ st, int j)
+{
+    using S = AxShape<N>;
+    constexpr int n1 = S::n1, np2 = S::np2, np3 = S::np3, epb = S::epb;
+    if constexpr (DOT) {
+        if (st->done_at <= j) return;
+    }
+    __shared__ double sq[epb][np2];
+    __shared__ double sr[epb][np2];
+    __shared__ double ss[epb][np2];
+    __shared__ double red[S::threads / 64];
+
+    const int t = threadIdx.x;
+    const bool lane_used = t < epb * np2;
+    const int el = lane_used ? t / np2 : epb - 1;  // spare lanes mirror the last element, inactive
+    const int ab = lane_used ? t - el * np2 : 0;
+    const int a = ab % n1, b = ab / n1;
+    const int64_t e = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * epb + el;
+    const bool active = lane_used && (e < E);
+    const int64_t eo = e < E ? e : E - 1;  // inactive lanes read a valid element and discard it
+
+    // rows and columns a, b of D, loaded once and kept in registers
+    double Da[n1], Db[n1], DaT[n1], DbT[n1];
+#pragma unroll
+    for (int m = 0; m < n1; ++m) {
+        Da[m] = Dm[a * n1 + m];
+        Db[m] = Dm[b * n1 + m];
+        DaT[m] = Dm[m * n1 + a];
+        DbT[m] = Dm[m * n1 + b];
+    }
+
+    // gather through Z: the (a,b) column of the element
+    uint32_t idx[n1];
+    double q[n1];
+    const uint32_t *me = reinterpret_cast<const uint32_t *>(map) + eo * np3 + ab;
+#pragma unroll
+    for (int c = 0; c < n1; ++c) idx[c] = me[c * np2];
+#pragma unroll
+    for (int c = 0; c < n1; ++c) q[c] = x[idx[c]];
+
+    const double *ge = geo + eo * kGeo * np3 + ab;
+    // G of layer c+1 is requested while layer c is computed: one layer in flight
+    double Gn[kGeo];
+#pragma unroll
+    for (int f = 0; f < kGeo; ++f) Gn[f] = ge[f * np3];
+    double ft[n1], yv[n1];
+#pragma unroll
+    for (int c = 0; c < n1; ++c) {
+        // keep each layer's instructions together: stops the scheduler from
+        // hoisting every layer's loads (and spilling them)
+        __builtin_amdgcn_sched_barrier(0);
+        double G[kGeo];
+#pragma unroll
+        for (int f = 0; f < kGeo; ++f) G[f] = Gn[f];
+        if (c + 1 < n1) {
+#pragma unroll
+            for (int f = 0; f < kGeo; ++f) Gn[f] = ge[f * np3 + (c + 1) * np2];
+        }
+        // t-derivative from registers; D[c][*] is uniform (scalar loads)
+        double qt = 0.0;
+#pragma unroll
+        for (int m = 0; m < n1; ++m) qt += Dm[c * n1 + m] * q[m];
+        if (lane_used) sq[el][ab] = q[c];
+        __syncthreads();
+        double qr = 0.0, qs = 0.0;
+#pragma unroll
+        for (int m = 0; m < n1; ++m) {
+            qr += Da[m] * sq[el][b * n1 + m];
+            qs += Db[m] * sq[el][m * n1 + a];
+        }
+        const double fr = G[0] * qr + G[1] * qs + G[2] * qt;
+        const double fs = G[1] * qr + G[3] * qs + G[4] * qt;
+        ft[c] = G[2] * qr + G[4] * qs + G[5] * qt;
+        pin(ft[c]);
+        double acc = lambda * G[6] * q[c];
+        if (lane_used) {
+            sr[el][ab] = fr;
+            ss[el][ab] = fs;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < n1; ++m) acc += DaT[m] * sr[el][b * n1 + m] + DbT[m] * ss[el][m * n1 + a];
+        pin(acc);
+        yv[c] = acc;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // t-part of D^T from registers
+#pragma unroll
+    for (int c = 0; c < n1; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < n1; ++m) s += Dm[m * n1 + c] * ft[m];
+        yv[c] += s;
+    }
+    // assemble through Z^T
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < n1; ++c) atomic_add_f64(&y[idx[c]], yv[c]);
+    }
+    if constexpr (DOT) {
+        double v = 0.0;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < n1; ++c) v += q[c] * yv[c];
+        }
+        v = block_sum(v, red);
+        if (t == 0) partial[blockIdx.x] = v;
+    }
+}
+
+template <int N>
+int ax_grid(int64_t E)
+{
+    return static_cast<int>((E + AxShape<N>::epb - 1) / AxShape<N>::epb);
+}
+
+template <int N>
+hb_status launch_ax_n(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
+                      int j, hipStream_t s)
+{
+    const int grid = ax_grid<N>(m->E);
+    if (grid == 0) return HB_OK;
+    if (st)
+        ax_kernel<N, true><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, m->geo, m->D, lambda, x, y, partial, st,
+                                                                j);
+    else
+        ax_kernel<N, false><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, m->geo, m->D, lambda, x, y, nullptr,
+                                                                 nullptr, 0);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+}  // namespace hb

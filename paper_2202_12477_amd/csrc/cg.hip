@@ -1,0 +1,230 @@
+// Kernels of the conjugate-gradient iteration (Algorithm 1; fused as in the
+// Conjugate gradient Iteration section, with every scalar kept on the device so
+// the host never waits inside an iteration).
+//
+// Iteration j is five launches on one stream:
+//   operator  Ap = A p, block partials of p.Ap              (ax*.hip)
+//   alpha     one block: p.Ap from the partials, alpha = rho_j / p.Ap
+//   residual  r -= alpha Ap, block partials of r.r
+//   beta      one block: rho_{j+1} = r.r, beta = rho_{j+1} / rho_j, history, stop test
+//   update    x += alpha p; p = r + beta p; Ap = 0 for the next assembly
+// Streaming kernels never wait for each other's blocks and issue no
+// device-scope fences: the single-block kernels finish the reductions in a
+// fixed order after the kernel boundary has made the partials visible.
+#include <climits>
+#include <cmath>
+
+#include "common.h"
+#include "reduce.h"
+
+namespace hb {
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kFinThreads = 1024;
+
+__device__ inline bool stopped(const CgState *st, int j) { return st->done_at <= j; }
+
+__global__ __launch_bounds__(kVecThreads) void zero_kernel(double *__restrict__ v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = 0.0;
+}
+
+__global__ void setup_state_kernel(CgState *st, int max_iter, double rtol)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->bb = st->alpha = st->beta = st->pAp = 0.0;
+    st->rtol = rtol;
+    st->max_iter = max_iter;
+    st->done_at = INT_MAX;
+    st->iters = 0;
+    st->status = HB_OK;
+}
+
+// r0 = b - A x0 (Ap holds A x0 unless x0 = 0), p = r0, Ap = 0; partials of r0.r0 and b.b.
+__global__ __launch_bounds__(kVecThreads) void init_kernel(int64_t n, const double *__restrict__ b,
+                                                          double *__restrict__ x, double *__restrict__ r,
+                                                          double *__restrict__ p, double *__restrict__ Ap,
+                                                          int x0_zero, double *__restrict__ partial)
+{
+    __shared__ double red[kVecThreads / 64];
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double bi = b[i];
+        const double ri = x0_zero ? bi : bi - Ap[i];
+        r[i] = ri;
+        p[i] = ri;
+        Ap[i] = 0.0;
+        if (x0_zero) x[i] = 0.0;
+        rr += ri * ri;
+        bb += bi * bi;
+    }
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = rr;
+        partial[gridDim.x + blockIdx.x] = bb;
+    }
+}
+
+__global__ __launch_bounds__(kFinThreads) void init_finish_kernel(const double *__restrict__ partial, int nblk,
+                                                                 CgState *st, double *__restrict__ rho,
+                                                                 double *__restrict__ hist)
+{
+    __shared__ double red[kFinThreads / 64];
+    const double rho0 = sum_partials(partial, nblk, red);
+    const double bb = sum_partials(partial + nblk, nblk, red);
+    if (threadIdx.x != 0) return;
+    st->bb = bb;
+    rho[0] = rho0;
+    hist[0] = sqrt(rho0);
+    if (!isfinite(rho0)) {
+        st->done_at = 0;
+        st->status = HB_ERR_NONFINITE;
+    } else if (rho0 == 0.0 || (st->rtol >= 0.0 && sqrt(rho0) <= st->rtol * sqrt(bb))) {
+        st->done_at = 0;  // already solved
+    } else if (st->max_iter == 0) {
+        st->done_at = 0;
+        st->status = st->rtol >= 0.0 ? HB_ERR_NOT_CONVERGED : HB_OK;
+    }
+}
+
+// alpha = rho_j / p.Ap, or stop on breakdown (p.Ap <= 0 or not finite).
+__global__ __launch_bounds__(kFinThreads) void alpha_kernel(const double *__restrict__ partial, int nblk, CgState *st,
+                                                           const double *__restrict__ rho, int j)
+{
+    if (stopped(st, j)) return;
+    __shared__ double red[kFinThreads / 64];
+    const double pAp = sum_partials(partial, nblk, red);
+    if (threadIdx.x != 0) return;
+    st->pAp = pAp;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+        st->done_at = j;
+        st->status = HB_ERR_BREAKDOWN;
+    } else {
+        st->alpha = rho[j] / pAp;
+    }
+}
+
+// r -= alpha Ap; partials of r.r.
+__global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, double *__restrict__ r,
+                                                              const double *__restrict__ Ap,
+                                                              double *__restrict__ partial, const CgState *st, int j)
+{
+    if (stopped(st, j)) return;
+    __shared__ double red[kVecThreads / 64];
+    const double alpha = st->alpha;
+    double rr = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ri = r[i] - alpha * Ap[i];
+        r[i] = ri;
+        rr += ri * ri;
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = rr;
+}
+
+// rho_{j+1} = r.r, beta, history, convergence / iteration-cap test.
+__global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restrict__ partial, int nblk, CgState *st,
+                                                          double *__restrict__ rho, double *__restrict__ hist, int j)
+{
+    if (stopped(st, j)) return;
+    __shared__ double red[kFinThreads / 64];
+    const double rho_new = sum_partials(partial, nblk, red);
+    if (threadIdx.x != 0) return;
+    st->beta = rho_new / rho[j];
+    rho[j + 1] = rho_new;
+    hist[j + 1] = sqrt(rho_new);
+    st->iters = j + 1;
+    // this iteration's update still runs (it tests done_at <= j); later ones do not
+    if (!isfinite(rho_new)) {
+        st->done_at = j + 1;
+        st->status = HB_ERR_BREAKDOWN;
+    } else if (rho_new == 0.0 || (st->rtol >= 0.0 && sqrt(rho_new) <= st->rtol * sqrt(st->bb))) {
+        st->done_at = j + 1;
+        st->status = HB_OK;
+    } else if (j + 1 >= st->max_iter) {
+        st->done_at = j + 1;
+        st->status = st->rtol >= 0.0 ? HB_ERR_NOT_CONVERGED : HB_OK;
+    }
+}
+
+// x += alpha p; p = r + beta p; Ap = 0 (the next operator call assembles into it).
+__global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *__restrict__ x, double *__restrict__ p,
+                                                            const double *__restrict__ r, double *__restrict__ Ap,
+                                                            const CgState *st, int j)
+{
+    if (stopped(st, j)) return;
+    const double alpha = st->alpha, beta = st->beta;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double pi = p[i];
+        x[i] += alpha * pi;
+        p[i] = r[i] + beta * pi;
+        Ap[i] = 0.0;
+    }
+}
+
+}  // namespace
+
+int vec_blocks(int64_t n)
+{
+    const int64_t want = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
+    return static_cast<int>(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+}
+
+hb_status launch_zero(double *v, int64_t n, hipStream_t s)
+{
+    if (n == 0) return HB_OK;
+    zero_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(v, n);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_setup_state(CgState *st, int max_iter, double rtol, hipStream_t s)
+{
+    setup_state_kernel<<<1, 64, 0, s>>>(st, max_iter, rtol);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p, double *Ap, int x0_zero,
+                         CgWork &w, CgState *st, hipStream_t s)
+{
+    const int g = vec_blocks(n);
+    init_kernel<<<g, kVecThreads, 0, s>>>(n, b, x, r, p, Ap, x0_zero, w.part_vec);
+    init_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, st, w.rho, w.hist);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, int j, hipStream_t s)
+{
+    alpha_kernel<<<1, kFinThreads, 0, s>>>(w.part_ax, ax_grid, st, w.rho, j);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_residual(int64_t n, double *r, const double *Ap, CgWork &w, CgState *st, int j, hipStream_t s)
+{
+    residual_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, w.part_vec, st, j);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, int j, hipStream_t s)
+{
+    beta_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, vec_blocks(n), st, w.rho, w.hist, j);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, double *Ap, CgState *st, int j,
+                           hipStream_t s)
+{
+    update_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, st, j);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+}  // namespace hb

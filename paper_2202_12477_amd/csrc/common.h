@@ -1,0 +1,108 @@
+// Internal declarations shared by the HIP translation units of libhbmi.
+// Not installed; the public interface is include/hbmi.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "hbmi.h"
+
+namespace hb {
+
+constexpr int kMaxN = 15;
+constexpr int kGeo = 7;  // G_rr, G_rs, G_rt, G_ss, G_st, G_tt, c
+
+// Thread-local error message behind hb_last_error().
+void set_error(const std::string &msg);
+hb_status fail(hb_status st, const std::string &msg);
+hb_status hip_fail(hipError_t err, const char *what);
+
+#define HB_HIP(call)                                      \
+    do {                                                  \
+        hipError_t err_ = (call);                         \
+        if (err_ != hipSuccess) return hb::hip_fail(err_, #call); \
+    } while (0)
+
+// Device-resident state of one CG solve (Algorithm 1).  Scalars never leave
+// the device.  Every launch of iteration j receives j and returns at once when
+// done_at <= j, so a fixed sequence of launches can run past convergence
+// harmlessly.  Each field is written only by a single-block kernel and read by
+// later kernels, so no kernel reads what it writes.
+struct CgState {
+    double bb;         // b . b
+    double alpha;      // alpha of the current iteration
+    double beta;       // beta of the current iteration
+    double pAp;        // p . A p of the current iteration
+    double rtol;       // < 0 in fixed-iteration mode
+    int32_t max_iter;
+    int32_t done_at;   // iterations j >= done_at do not run (INT32_MAX while running)
+    int32_t iters;     // completed iterations
+    int32_t status;    // hb_status of the solve
+};
+
+// Per-mesh CG workspace (device), allocated on first use.
+struct CgWork {
+    int64_t n = 0;         // N_G it was sized for
+    int32_t hist_len = 0;  // entries in hist
+    double *r = nullptr, *p = nullptr, *Ap = nullptr;
+    double *part_ax = nullptr;  // operator block partials of p.Ap (>= operator grid)
+    double *part_vec = nullptr; // vector-kernel block partials (>= 2 * vector grid)
+    int32_t part_ax_len = 0, part_vec_len = 0;
+    double *rho = nullptr;      // r_j . r_j, j = 0..max_iter
+    double *hist = nullptr;     // ||r_j||, j = 0..max_iter
+    CgState *state = nullptr;
+    CgState *host_state = nullptr;  // pinned mirror for read-back
+    size_t bytes = 0;               // device bytes held (counted in the mesh's device_bytes)
+};
+
+}  // namespace hb
+
+struct hb_mesh_s {
+    hb_mesh_desc desc;
+    int N = 0;
+    int64_t E = 0, NL = 0, NG = 0;
+    int32_t *map = nullptr;   // [E][(N+1)^3] global index per local node (rows of Z)
+    double *geo = nullptr;    // [E][7][(N+1)^3]
+    double *D = nullptr;      // [(N+1)^2] row-major
+    double *xi = nullptr, *w = nullptr;  // device copies of the GLL nodes and weights
+    double h_xi[hb::kMaxN + 1], h_w[hb::kMaxN + 1], h_D[(hb::kMaxN + 1) * (hb::kMaxN + 1)];
+    hb::CgWork cg;
+    size_t device_bytes = 0;
+};
+
+namespace hb {
+
+// Host-side 1D basis (basis.cpp): GLL nodes ascending, weights, D[i][j] = l_j'(xi_i).
+void gll_basis(int N, double *xi, double *w, double *D);
+
+// Setup kernels (setup.hip).
+hb_status build_geometry(hb_mesh_s *m, hipStream_t s);
+hb_status launch_rhs(int64_t n, uint64_t seed, double *b, hipStream_t s);
+
+// Operator (ax*.hip).  y += A x (y is assembled by atomic addition, so a
+// fresh result needs y = 0 first).  With st != nullptr this is iteration j of
+// CG: it returns at once if the solve has stopped, and each block also writes
+// its share of sum_e x_e . y_e (= x . A x) to partial[block].
+hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
+                    int j, hipStream_t s);
+int ax_blocks(const hb_mesh_s *m);
+
+// Vector kernels of CG (cg.hip).
+int vec_blocks(int64_t n);
+hb_status launch_zero(double *v, int64_t n, hipStream_t s);
+hb_status launch_cg_setup_state(CgState *st, int max_iter, double rtol, hipStream_t s);
+hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p, double *Ap, int x0_zero,
+                         CgWork &w, CgState *st, hipStream_t s);
+hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, int j, hipStream_t s);
+hb_status launch_cg_residual(int64_t n, double *r, const double *Ap, CgWork &w, CgState *st, int j, hipStream_t s);
+hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, int j, hipStream_t s);
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, double *Ap, CgState *st, int j,
+                           hipStream_t s);
+
+// 8:1 streaming probe (stream.hip).
+hb_status launch_stream_probe(const double *in, double *out, int64_t n, hipStream_t s);
+
+}  // namespace hb
