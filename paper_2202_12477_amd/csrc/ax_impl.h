@@ -13,8 +13,10 @@
 //   - each block holds EPB elements (EPB*(N+1)^2 <= 256 threads), so N=7 is
 //     one wave per element and low orders pack several elements per wave.
 // HBM streams: map (4 B/node) and the 7 geometric values (56 B/node) once,
-// coalesced per layer; x through an indirect (cache-friendly) gather; y by
-// device-scope FP64 atomic adds into a zeroed vector.
+// coalesced per layer (G non-temporal, two layers ahead); x through an
+// indirect (cache-friendly) gather; y by device-scope FP64 atomic adds into a
+// zeroed vector (atomics on every node: mixing plain stores into lines that
+// other elements update atomically measured far slower).
 #pragma once
 
 #include "common.h"
@@ -92,11 +94,14 @@ void ax_kernel(
 #pragma unroll
     for (int c = 0; c < n1; ++c) q[c] = x[idx[c]];
 
+    // G is streamed once: non-temporal loads keep it from evicting x and y from
+    // the caches.  Layers c+1 and c+2 are in flight while layer c is computed.
     const double *ge = geo + eo * kGeo * np3 + ab;
-    // G of layer c+1 is requested while layer c is computed: one layer in flight
-    double Gn[kGeo];
+    double Gn[kGeo], Gnn[kGeo];
 #pragma unroll
-    for (int f = 0; f < kGeo; ++f) Gn[f] = ge[f * np3];
+    for (int f = 0; f < kGeo; ++f) Gn[f] = __builtin_nontemporal_load(&ge[f * np3]);
+#pragma unroll
+    for (int f = 0; f < kGeo; ++f) Gnn[f] = __builtin_nontemporal_load(&ge[f * np3 + np2]);  // n1 >= 2
     double ft[n1], yv[n1];
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
@@ -106,9 +111,11 @@ void ax_kernel(
         double G[kGeo];
 #pragma unroll
         for (int f = 0; f < kGeo; ++f) G[f] = Gn[f];
-        if (c + 1 < n1) {
 #pragma unroll
-            for (int f = 0; f < kGeo; ++f) Gn[f] = ge[f * np3 + (c + 1) * np2];
+        for (int f = 0; f < kGeo; ++f) Gn[f] = Gnn[f];
+        if (c + 2 < n1) {
+#pragma unroll
+            for (int f = 0; f < kGeo; ++f) Gnn[f] = __builtin_nontemporal_load(&ge[f * np3 + (c + 2) * np2]);
         }
         // t-derivative from registers; D[c][*] is uniform (scalar loads)
         double qt = 0.0;
