@@ -54,6 +54,16 @@ typedef enum {
  * A = S + lambda*I exactly as eq. (poisson) writes it. */
 typedef enum { HB_MASS_GWJ = 0, HB_MASS_INVDEG = 1 } hb_mass;
 
+/* Mesh flags. */
+enum { HB_MESH_FP32 = 1 /* also keep FP32 geometric factors and D, for hb_ax_f32 and FP32 refinement */ };
+
+/* Precision of hb_cg_solve. */
+typedef enum {
+    HB_PREC_FP64 = 0,     /* Algorithm 1 with the FP64 operator */
+    HB_PREC_FP32_IR = 1,  /* FP64 iterative refinement, each correction solved by CG with the FP32 operator */
+    HB_PREC_FP32_RR = 2   /* one CG with the FP32 operator and FP64 residual replacement */
+} hb_prec;                /* both mixed modes need HB_MESH_FP32 */
+
 typedef struct hb_mesh_s *hb_mesh;
 
 /* Box mesh on [0,1]^3 (NekBone section: a regular mesh of E hexahedra with
@@ -67,7 +77,7 @@ typedef struct {
     double jitter;      /* 0 <= jitter < 0.5 (0: affine box) */
     uint64_t seed;      /* jitter seed */
     int32_t mass;       /* hb_mass */
-    int32_t reserved;   /* must be 0 */
+    int32_t flags;      /* 0 or HB_MESH_FP32 */
 } hb_mesh_desc;
 
 typedef struct {
@@ -83,7 +93,9 @@ typedef struct {
  * matrix D (NekBone section), the scatter map Z as int32 [E][(N+1)^3], and the
  * geometric factors G_rr, G_rs, G_rt, G_ss, G_st, G_tt and c as FP64
  * [E][7][(N+1)^3] (G_dd' = w_a w_b w_c J sum_i dxi_d/dx_i dxi_d'/dx_i, the
- * metric tensor combined with the GLL weights).  Synchronises `stream`.
+ * metric tensor combined with the GLL weights).  With HB_MESH_FP32 the mesh
+ * also keeps the factors and D rounded once to FP32 (28 more bytes per local
+ * node).  Synchronises `stream`.
  * Errors: HB_ERR_INVALID_ARG (bad desc, N_G or N_L >= 2^31, non-positive
  * Jacobian), HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE.  *out is NULL on failure. */
 hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out);
@@ -121,21 +133,36 @@ hb_status hb_ax(hb_mesh mesh, double lambda, const double *dev_x, double *dev_y,
  * first (hb_ax = clear y, then this).  Same arguments and rules as hb_ax. */
 hb_status hb_ax_add(hb_mesh mesh, double lambda, const double *dev_x, double *dev_y, void *stream);
 
+/* y = A x with the FP32 operator: x is read as FP64 and rounded to FP32; the
+ * FP32 geometric factors and D, FP32 arithmetic and FP32 atomic assembly give
+ * y (FP32, N_G entries, overwritten).  Needs a mesh built with HB_MESH_FP32.
+ * Same rules as hb_ax otherwise.  The paper is FP64 throughout; this is the
+ * reduced-precision operator of the mixed-precision solver. */
+hb_status hb_ax_f32(hb_mesh mesh, double lambda, const double *dev_x, float *dev_y, void *stream);
+
 /* Options of hb_cg_solve (Algorithm 1). */
 typedef struct {
-    int32_t max_iter;    /* iteration cap (>= 0); in fixed mode the exact count */
-    int32_t fixed_iters; /* 1: run exactly max_iter iterations (the benchmark's 100); 0: stop on rtol */
-    double rtol;         /* stop once ||r_j||_2 <= rtol ||b||_2 (recursive residual) */
+    int32_t max_iter;    /* FP64: iteration cap (>= 0), in fixed mode the exact count;
+                            FP32_IR: cap on the total inner iterations */
+    int32_t fixed_iters; /* 1: run exactly max_iter iterations (the benchmark's 100); 0: stop on rtol.
+                            FP32_IR requires 0. */
+    double rtol;         /* FP64: stop once ||r_j|| <= rtol ||b|| (recursive residual);
+                            FP32_IR: stop once ||b - A x|| <= rtol ||b|| with the FP64 operator */
     int32_t x0_zero;     /* 1: ignore dev_x on entry and start from x0 = 0 (r0 = b, no operator call) */
     int32_t check_every; /* tolerance mode: read the device state back every this many iterations (<=0: 25) */
+    int32_t prec;        /* hb_prec */
+    int32_t max_outer;   /* FP32_IR: cap on refinement steps (<=0: 60) */
+    double inner_rtol;   /* FP32_IR: each inner solve stops at ||r_in|| <= inner_rtol ||r|| (<=0: 1e-3) */
 } hb_cg_opts;
 
 typedef struct {
-    int32_t iters;       /* iterations completed */
+    int32_t iters;       /* FP64: iterations completed; FP32_IR: inner iterations in total */
     int32_t status;      /* hb_status of the solve */
     double res0;         /* ||r_0|| */
-    double res;          /* ||r_iters|| (recursive) */
+    double res;          /* FP64: ||r_iters|| (recursive); FP32_IR: ||b - A x|| (FP64 operator) at exit */
     double bnorm;        /* ||b|| */
+    int32_t outer_iters; /* FP32_IR: refinement steps taken (0 in FP64 mode) */
+    int32_t fp64_iters;  /* FP32_IR: FP64 CG iterations run after the refinement stalled (0 if it did not) */
 } hb_cg_result;
 
 /* Algorithm 1 on the assembled system A x = b: r0 = b - A x0, p = r0; per
@@ -145,7 +172,26 @@ typedef struct {
  * with a fixed final order.  Stops early (status) on p.Ap <= 0 (BREAKDOWN),
  * a non-finite r0.r0 (NONFINITE) or r.r == 0 (exact solution, OK).
  * dev_b: N_G doubles; dev_x: N_G doubles, initial guess in, solution out.
- * host_res_hist: NULL or room for max_iter+1 doubles, receives ||r_j||, j = 0..iters.
+ * host_res_hist: NULL or room for max_iter+1 doubles, receives ||r_j||, j = 0..iters
+ * (FP32_IR: the true residual ||b - A x_k|| of each refinement step k = 0..outer_iters).
+ *
+ * FP32_IR (mixed precision): x_0 = x0; repeat { r = b - A x_k with the FP64
+ * operator; stop if ||r|| <= rtol ||b||; solve A_32 d = r by CG (FP32 operator,
+ * FP64 vectors, dot products, residual updates) from d = 0 to
+ * ||r_in|| <= inner_rtol ||r||; x_{k+1} = x_k + d }.  If a refinement step
+ * reduces ||r|| by less than a factor 2 (the FP32 operator's error times the
+ * condition number is too large), the solve continues with FP64 CG from x and
+ * reports it in fp64_iters.
+ *
+ * FP32_RR (mixed precision, keeps the Krylov sequence): CG whose operator is
+ * the FP32 one; whenever the recursive ||r|| has dropped by inner_rtol since
+ * the last replacement, r is replaced by b - A x computed with the FP64
+ * operator (residual replacement, van der Vorst & Ye 2000) and the iteration
+ * continues with the same search direction.  It stops when a replacement gives
+ * ||b - A x|| <= rtol ||b||.  If a replacement shows less than a halving of the
+ * true residual, the remaining iterations use the FP64 operator (fp64_iters).
+ * outer_iters counts the replacements; iters the CG iterations in total;
+ * host_res_hist receives the true residual at the start and at each replacement.
  * Synchronises `stream` before returning.  Returns the solve's status
  * (HB_OK, HB_ERR_NOT_CONVERGED, HB_ERR_BREAKDOWN, HB_ERR_NONFINITE) or an
  * argument/device error. */

@@ -27,11 +27,15 @@ HB_ERR_BUSY = 8
 
 MASS_GWJ = 0
 MASS_INVDEG = 1
+MESH_FP32 = 1
+PREC_FP64 = 0
+PREC_FP32_IR = 1
+PREC_FP32_RR = 2
 
 # Every entry point of include/hbmi.h, in declaration order.
 EXPORTS = (
     "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax",
-    "hb_ax_add", "hb_cg_solve", "hb_stream_probe", "hb_status_string", "hb_last_error",
+    "hb_ax_add", "hb_ax_f32", "hb_cg_solve", "hb_stream_probe", "hb_status_string", "hb_last_error",
 )
 
 
@@ -44,7 +48,7 @@ class HbError(RuntimeError):
 class _MeshDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("jitter", ctypes.c_double), ("seed", ctypes.c_uint64), ("mass", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 class _MeshInfo(ctypes.Structure):
@@ -54,12 +58,14 @@ class _MeshInfo(ctypes.Structure):
 
 class _CgOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
 
 
 class _CgResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("res0", ctypes.c_double),
-                ("res", ctypes.c_double), ("bnorm", ctypes.c_double)]
+                ("res", ctypes.c_double), ("bnorm", ctypes.c_double), ("outer_iters", ctypes.c_int32),
+                ("fp64_iters", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,6 +89,7 @@ def lib() -> ctypes.CDLL:
         "hb_rhs_uniform": [i64, u64, vp, vp],
         "hb_ax": [vp, f64, vp, vp, vp],
         "hb_ax_add": [vp, f64, vp, vp, vp],
+        "hb_ax_f32": [vp, f64, vp, vp, vp],
         "hb_cg_solve": [vp, f64, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp, vp],
         "hb_stream_probe": [vp, vp, i64, vp],
     }
@@ -136,6 +143,8 @@ class CgResult:
     res0: float
     res: float
     bnorm: float
+    outer_iters: int = 0
+    fp64_iters: int = 0
     history: "list[float] | None" = None
 
 
@@ -143,8 +152,8 @@ class Mesh:
     """A device-resident box mesh (hb_mesh_create / hb_mesh_destroy)."""
 
     def __init__(self, nx: int, ny: int, nz: int, N: int, jitter: float = 0.0, seed: int = 0,
-                 mass: int = MASS_GWJ, stream=None):
-        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, 0)
+                 mass: int = MASS_GWJ, fp32: bool = False, stream=None):
+        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, MESH_FP32 if fp32 else 0)
         h = ctypes.c_void_p()
         _check(lib().hb_mesh_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)), "hb_mesh_create")
         self._h = h
@@ -206,24 +215,37 @@ class Mesh:
                "hb_ax_add")
         return y
 
+    def ax_f32(self, lam: float, x, y, stream=None):
+        """y = A_32 x with the FP32 operator (x float64, y float32; mesh built with fp32=True)."""
+        import torch
+
+        if x.numel() != self.NG or y.numel() != self.NG:
+            raise ValueError("vectors must have N_G entries")
+        _check(lib().hb_ax_f32(self.handle, lam, _ptr(x, torch.float64), _ptr(y, torch.float32), _stream(stream)),
+               "hb_ax_f32")
+        return y
+
     def cg(self, lam: float, b, x, *, max_iter: int = 100, fixed_iters: bool = True, rtol: float = 0.0,
-           x0_zero: bool = True, check_every: int = 0, history: bool = True, stream=None,
+           x0_zero: bool = True, check_every: int = 0, history: bool = True, prec: int = PREC_FP64,
+           max_outer: int = 0, inner_rtol: float = 0.0, stream=None,
            raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)) -> CgResult:
-        """Algorithm 1 on the device; x holds the initial guess (unless x0_zero) and the result."""
+        """Algorithm 1 on the device (prec=PREC_FP64), or FP64 refinement around the FP32-operator CG
+        (prec=PREC_FP32_IR); x holds the initial guess (unless x0_zero) and the result."""
         import torch
 
         if b.numel() != self.NG or x.numel() != self.NG:
             raise ValueError("vectors must have N_G entries")
-        opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every)
+        opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, max_outer, inner_rtol)
         res = _CgResult()
         hist = (ctypes.c_double * (max_iter + 1))() if history else None
         st = lib().hb_cg_solve(self.handle, lam, _ptr(b, torch.float64), _ptr(x, torch.float64), ctypes.byref(opts),
                                ctypes.byref(res), hist, _stream(stream))
         if st in raise_on:
             _check(st, "hb_cg_solve")
-        out = CgResult(res.iters, res.status, res.res0, res.res, res.bnorm)
+        out = CgResult(res.iters, res.status, res.res0, res.res, res.bnorm, res.outer_iters, res.fp64_iters)
         if history:
-            out.history = list(hist[: res.iters + 1])
+            k = res.outer_iters if prec != PREC_FP64 else res.iters
+            out.history = list(hist[: min(k, max_iter) + 1])
         return out
 
 

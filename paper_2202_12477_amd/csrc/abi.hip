@@ -38,10 +38,12 @@ hb_status dev_alloc(T **p, size_t count, size_t *tally)
 void free_cg(hb_mesh_s *m)
 {
     CgWork &w = m->cg;
-    for (double *p : {w.r, w.p, w.Ap, w.part_ax, w.part_vec, w.rho, w.hist})
+    for (double *p : {w.r, w.p, w.Ap, w.part_ax, w.part_vec, w.rho, w.hist, w.rout, w.d, w.dnorm})
         if (p) (void)hipFree(p);
+    if (w.Ap32) (void)hipFree(w.Ap32);
     if (w.state) (void)hipFree(w.state);
     if (w.host_state) (void)hipHostFree(w.host_state);
+    if (w.host_norm) (void)hipHostFree(w.host_norm);
     m->device_bytes -= w.bytes;
     w = CgWork{};
 }
@@ -53,30 +55,38 @@ void free_mesh(hb_mesh_s *m)
     if (m->map) (void)hipFree(m->map);
     for (double *p : {m->geo, m->D, m->xi, m->w})
         if (p) (void)hipFree(p);
+    for (float *p : {m->geo32, m->D32})
+        if (p) (void)hipFree(p);
     delete m;
 }
 
 // Size the CG workspace for this mesh and iteration cap.
-hb_status ensure_cg(hb_mesh_s *m, int max_iter)
+hb_status ensure_cg(hb_mesh_s *m, int max_iter, bool mixed)
 {
     CgWork &w = m->cg;
     const int need_ax = ax_blocks(m), need_vec = 2 * vec_blocks(m->NG);
-    if (w.r && w.n == m->NG && w.hist_len >= max_iter + 1 && w.part_ax_len >= need_ax && w.part_vec_len >= need_vec)
+    if (w.r && w.n == m->NG && w.hist_len >= max_iter + 1 && w.part_ax_len >= need_ax &&
+        w.part_vec_len >= need_vec && (!mixed || w.Ap32))
         return HB_OK;
     const int hist_len = std::max(max_iter + 1, w.hist_len);
+    mixed = mixed || w.Ap32;
     if (w.r) free_cg(m);
     size_t tally = 0;
     hb_status st;
     if ((st = dev_alloc(&w.r, m->NG, &tally)) || (st = dev_alloc(&w.p, m->NG, &tally)) ||
         (st = dev_alloc(&w.Ap, m->NG, &tally)) || (st = dev_alloc(&w.part_ax, need_ax, &tally)) ||
         (st = dev_alloc(&w.part_vec, need_vec, &tally)) || (st = dev_alloc(&w.rho, hist_len, &tally)) ||
-        (st = dev_alloc(&w.hist, hist_len, &tally)) || (st = dev_alloc(&w.state, 1, &tally))) {
+        (st = dev_alloc(&w.hist, hist_len, &tally)) || (st = dev_alloc(&w.state, 1, &tally)) ||
+        (st = dev_alloc(&w.dnorm, 1, &tally)) ||
+        (mixed && ((st = dev_alloc(&w.rout, m->NG, &tally)) || (st = dev_alloc(&w.d, m->NG, &tally)) ||
+                   (st = dev_alloc(&w.Ap32, m->NG, &tally))))) {
         w.bytes = tally;
         m->device_bytes += tally;
         free_cg(m);
         return st;
     }
-    if (hipHostMalloc(reinterpret_cast<void **>(&w.host_state), sizeof(CgState), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&w.host_state), sizeof(CgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&w.host_norm), sizeof(double), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         w.bytes = tally;
         m->device_bytes += tally;
@@ -90,6 +100,182 @@ hb_status ensure_cg(hb_mesh_s *m, int max_iter)
     w.bytes = tally;
     m->device_bytes += tally;
     return HB_OK;
+}
+
+// The operator for each output type: FP64 operator into double, FP32 into float.
+hb_status apply_op(const hb_mesh_s *m, double l, const double *x, double *y, double *part, CgState *st, int j,
+                   hipStream_t s)
+{
+    return launch_ax(m, l, x, y, part, st, j, s);
+}
+hb_status apply_op(const hb_mesh_s *m, double l, const double *x, float *y, double *part, CgState *st, int j,
+                   hipStream_t s)
+{
+    return launch_ax32(m, l, x, y, part, st, j, s);
+}
+
+hb_status read_state(CgWork &w, hipStream_t s)
+{
+    HB_HIP(hipMemcpyAsync(w.host_state, w.state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    HB_HIP(hipStreamSynchronize(s));
+    return HB_OK;
+}
+
+// Enqueue CG iterations j0, j0+1, ... with the operator whose output type is
+// TAp until the device state stops the solve or max_iter is reached; the state
+// is left in w.host_state.  rtol < 0 (fixed count) enqueues everything at once;
+// otherwise the state is read back every `check_every` iterations.
+template <typename TAp>
+hb_status cg_iterate(hb_mesh_s *m, double lambda, double *x, TAp *Ap, int j0, int max_iter, bool fixed,
+                     int check_every, hipStream_t s)
+{
+    CgWork &w = m->cg;
+    const int64_t n = m->NG;
+    const int axg = ax_blocks(m);
+    hb_status st;
+    auto enqueue_iteration = [&](int j) -> hb_status {
+        hb_status e;
+        if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, j, s))) return e;
+        if ((e = launch_cg_alpha(w, axg, w.state, j, s))) return e;
+        if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, j, s))) return e;
+        if ((e = launch_cg_beta(n, w, w.state, j, s))) return e;
+        return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.state, j, s);
+    };
+    const int chunk = fixed ? std::max(max_iter - j0, 1) : (check_every > 0 ? check_every : 25);
+    int enqueued = j0;
+    if (!fixed && (st = read_state(w, s))) return st;
+    while (enqueued < max_iter && (fixed || w.host_state->done_at > enqueued)) {
+        const int k = std::min(chunk, max_iter - enqueued);
+        for (int i = 0; i < k; ++i)
+            if ((st = enqueue_iteration(enqueued + i))) return st;
+        enqueued += k;
+        if (!fixed && (st = read_state(w, s))) return st;
+    }
+    return read_state(w, s);
+}
+
+// Algorithm 1: r0 = b - A x0, p = r0, then iterations until the stop test.
+template <typename TAp>
+hb_status run_cg(hb_mesh_s *m, double lambda, const double *b, double *x, TAp *Ap, int x0_zero, int max_iter,
+                 double rtol, int check_every, hipStream_t s)
+{
+    CgWork &w = m->cg;
+    const int64_t n = m->NG;
+    hb_status st;
+    if ((st = launch_cg_setup_state(w.state, max_iter, rtol, s))) return st;
+    if (!x0_zero) {
+        if ((st = launch_zero(Ap, n, s)) || (st = apply_op(m, lambda, x, Ap, nullptr, nullptr, 0, s))) return st;
+    }
+    if ((st = launch_cg_init<TAp>(n, b, x, w.r, w.p, Ap, x0_zero, w, w.state, s))) return st;
+    return cg_iterate<TAp>(m, lambda, x, Ap, 0, max_iter, rtol < 0.0, check_every, s);
+}
+
+// ||b - A x||^2 with the FP64 operator (t = A x in w.Ap, r = b - t in w.rout).
+hb_status true_residual_sq(hb_mesh_s *m, double lambda, const double *b, const double *x, hipStream_t s, double *out)
+{
+    CgWork &w = m->cg;
+    hb_status st;
+    if ((st = launch_zero(w.Ap, m->NG, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, 0, s)) ||
+        (st = launch_residual_norm(m->NG, b, w.Ap, w.rout, w, w.dnorm, s)))
+        return st;
+    HB_HIP(hipMemcpyAsync(w.host_norm, w.dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HB_HIP(hipStreamSynchronize(s));
+    *out = *w.host_norm;
+    return HB_OK;
+}
+
+hb_status read_norm(CgWork &w, hipStream_t s, double *out)
+{
+    HB_HIP(hipMemcpyAsync(w.host_norm, w.dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HB_HIP(hipStreamSynchronize(s));
+    *out = *w.host_norm;
+    return HB_OK;
+}
+
+// CG with the FP32 operator and FP64 residual replacement: one Krylov
+// sequence; whenever the recursive residual has dropped by inner_rtol since
+// the last replacement, r is recomputed as b - A x with the FP64 operator and
+// the iteration continues with the same search direction.  If a replacement
+// shows less than a halving of the true residual, the FP32 operator has
+// reached its accuracy limit and the iteration continues with the FP64 one.
+hb_status solve_replace(hb_mesh_s *m, double lambda, const double *b, double *x, const hb_cg_opts *opts,
+                        hb_cg_result *result, double *hist, hipStream_t s)
+{
+    CgWork &w = m->cg;
+    const int64_t n = m->NG;
+    const double eta = opts->inner_rtol > 0.0 ? opts->inner_rtol : 1e-3;
+    const int max_outer = opts->max_outer > 0 ? opts->max_outer : 1000000;
+    hb_status st;
+    if ((st = launch_cg_setup_state(w.state, opts->max_iter, opts->rtol, s))) return st;
+    if (!opts->x0_zero) {
+        if ((st = launch_zero(w.Ap, n, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, 0, s))) return st;
+    }
+    if ((st = launch_cg_init<double>(n, b, x, w.r, w.p, w.Ap, opts->x0_zero, w, w.state, s)) ||
+        (st = launch_zero(w.Ap32, n, s)) || (st = read_state(w, s)))
+        return st;
+    double rho0 = 0.0;
+    HB_HIP(hipMemcpy(&rho0, w.rho, sizeof(double), hipMemcpyDeviceToHost));
+    const double bnorm = std::sqrt(w.host_state->bb);
+    double res = std::sqrt(rho0), ref = res;
+    const double res0 = res;
+    if (hist && opts->max_iter >= 0) hist[0] = res;
+    int j = 0, outer = 0, fp64_from = -1;
+    hb_status status = static_cast<hb_status>(w.host_state->status);
+    bool use32 = true;
+    if (w.host_state->done_at > 0) {
+        status = HB_ERR_NOT_CONVERGED;
+        if ((st = launch_cg_resume(w.state, std::max(eta * ref, opts->rtol * bnorm), s))) return st;
+        for (;;) {
+            st = use32 ? cg_iterate<float>(m, lambda, x, w.Ap32, j, opts->max_iter, false, opts->check_every, s)
+                       : cg_iterate<double>(m, lambda, x, w.Ap, j, opts->max_iter, false, opts->check_every, s);
+            if (st) return st;
+            j = w.host_state->iters;
+            const bool breakdown = w.host_state->status == HB_ERR_BREAKDOWN;
+            if (breakdown && !use32) {
+                status = HB_ERR_BREAKDOWN;
+                break;
+            }
+            // replacement: r = b - A x with the FP64 operator
+            double rr = 0.0;
+            if ((st = launch_zero(w.Ap, n, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, 0, s)) ||
+                (st = launch_cg_replace(n, b, w.Ap, w.r, w, w.state, j, w.dnorm, s)) || (st = read_norm(w, s, &rr)))
+                return st;
+            ++outer;
+            res = std::sqrt(rr);
+            if (hist && outer <= opts->max_iter) hist[outer] = res;
+            if (!std::isfinite(res)) {
+                status = HB_ERR_BREAKDOWN;
+                break;
+            }
+            if (res <= opts->rtol * bnorm) {
+                status = HB_OK;
+                break;
+            }
+            if (j >= opts->max_iter || outer >= max_outer) break;
+            if (use32 && (breakdown || res > 0.5 * ref)) {
+                use32 = false;
+                fp64_from = j;
+            }
+            // both operator outputs start the next segment at zero (w.Ap held A x)
+            if ((st = launch_zero(w.Ap, n, s)) || (st = launch_zero(w.Ap32, n, s))) return st;
+            ref = res;
+            if ((st = launch_cg_resume(w.state, use32 ? std::max(eta * ref, opts->rtol * bnorm) : opts->rtol * bnorm,
+                                       s)))
+                return st;
+        }
+    }
+    HB_HIP(hipStreamSynchronize(s));
+    if (result) {
+        *result = hb_cg_result{};
+        result->iters = j;
+        result->status = status;
+        result->res0 = res0;
+        result->res = res;
+        result->bnorm = bnorm;
+        result->outer_iters = outer;
+        result->fp64_iters = fp64_from >= 0 ? j - fp64_from : 0;
+    }
+    return status;
 }
 
 }  // namespace
@@ -141,7 +327,7 @@ hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out)
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: element counts must be >= 1");
     if (!(d.jitter >= 0.0 && d.jitter < 0.5)) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: jitter must be in [0, 0.5)");
     if (d.mass != HB_MASS_GWJ && d.mass != HB_MASS_INVDEG) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: bad mass kind");
-    if (d.reserved != 0) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: reserved field must be 0");
+    if (d.flags & ~HB_MESH_FP32) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: unknown flag");
     const int64_t n1 = d.N + 1;
     const double E_d = (double)d.nx * d.ny * d.nz;
     const double NL_d = E_d * n1 * n1 * n1;
@@ -178,6 +364,19 @@ hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out)
     if ((st = build_geometry(m, s))) {
         free_mesh(m);
         return st;
+    }
+    if (d.flags & HB_MESH_FP32) {
+        if ((st = dev_alloc(&m->geo32, kGeo * m->NL, &m->device_bytes)) ||
+            (st = dev_alloc(&m->D32, n1 * n1, &m->device_bytes)) ||
+            (st = launch_round_f32(m->geo, m->geo32, kGeo * m->NL, s)) ||
+            (st = launch_round_f32(m->D, m->D32, n1 * n1, s))) {
+            free_mesh(m);
+            return st;
+        }
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+            free_mesh(m);
+            return hip_fail(e, "hb_mesh_create: FP32 geometry");
+        }
     }
     *out = m;
     return HB_OK;
@@ -241,6 +440,19 @@ hb_status hb_ax_add(hb_mesh m, double lambda, const double *dev_x, double *dev_y
     return launch_ax(m, lambda, dev_x, dev_y, nullptr, nullptr, 0, static_cast<hipStream_t>(stream));
 }
 
+hb_status hb_ax_f32(hb_mesh m, double lambda, const double *dev_x, float *dev_y, void *stream)
+{
+    if (!m || !dev_x || !dev_y) return fail(HB_ERR_INVALID_ARG, "hb_ax_f32: null argument");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(HB_ERR_INVALID_ARG, "hb_ax_f32: lambda must be finite and > 0");
+    if (!m->geo32) return fail(HB_ERR_INVALID_ARG, "hb_ax_f32: the mesh was built without HB_MESH_FP32");
+    if (static_cast<const void *>(dev_x) == static_cast<const void *>(dev_y))
+        return fail(HB_ERR_INVALID_ARG, "hb_ax_f32: x and y must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hb_status st = launch_zero(dev_y, m->NG, s);
+    if (st) return st;
+    return launch_ax32(m, lambda, dev_x, dev_y, nullptr, nullptr, 0, s);
+}
+
 hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev_x, const hb_cg_opts *opts,
                       hb_cg_result *result, double *host_res_hist, void *stream)
 {
@@ -249,59 +461,113 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
     if (opts->max_iter < 0) return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: max_iter must be >= 0");
     if (!opts->fixed_iters && !(opts->rtol >= 0.0)) return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: rtol must be >= 0");
     if (dev_b == dev_x) return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: b and x must not alias");
+    if (opts->prec != HB_PREC_FP64 && opts->prec != HB_PREC_FP32_IR && opts->prec != HB_PREC_FP32_RR)
+        return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: unknown precision");
+    const bool mixed = opts->prec != HB_PREC_FP64;
+    if (mixed && opts->fixed_iters)
+        return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: mixed precision needs a tolerance (fixed_iters = 0)");
+    if (mixed && !m->geo32)
+        return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: mixed precision needs a mesh built with HB_MESH_FP32");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hb_status st = ensure_cg(m, opts->max_iter);
+    hb_status st = ensure_cg(m, opts->max_iter, mixed);
     if (st) return st;
     CgWork &w = m->cg;
-    const int64_t n = m->NG;
-    const double rtol = opts->fixed_iters ? -1.0 : opts->rtol;
-    if ((st = launch_cg_setup_state(w.state, opts->max_iter, rtol, s))) return st;
-    if (!opts->x0_zero) {
-        if ((st = launch_zero(w.Ap, n, s)) || (st = launch_ax(m, lambda, dev_x, w.Ap, nullptr, nullptr, 0, s))) return st;
+    if (opts->prec == HB_PREC_FP32_RR) return solve_replace(m, lambda, dev_b, dev_x, opts, result, host_res_hist, s);
+    if (!mixed) {
+        if ((st = run_cg<double>(m, lambda, dev_b, dev_x, w.Ap, opts->x0_zero, opts->max_iter,
+                                 opts->fixed_iters ? -1.0 : opts->rtol, opts->check_every, s)))
+            return st;
+        const CgState hs = *w.host_state;
+        double rho0 = 0.0, rho_last = 0.0;
+        HB_HIP(hipMemcpy(&rho0, w.rho, sizeof(double), hipMemcpyDeviceToHost));
+        HB_HIP(hipMemcpy(&rho_last, w.rho + hs.iters, sizeof(double), hipMemcpyDeviceToHost));
+        if (host_res_hist)
+            HB_HIP(hipMemcpy(host_res_hist, w.hist, sizeof(double) * (hs.iters + 1), hipMemcpyDeviceToHost));
+        if (result) {
+            *result = hb_cg_result{};
+            result->iters = hs.iters;
+            result->status = hs.status;
+            result->res0 = std::sqrt(rho0);
+            result->res = std::sqrt(rho_last);
+            result->bnorm = std::sqrt(hs.bb);
+        }
+        return static_cast<hb_status>(hs.status);
     }
-    if ((st = launch_cg_init(n, dev_b, dev_x, w.r, w.p, w.Ap, opts->x0_zero, w, w.state, s))) return st;
 
-    const int axg = ax_blocks(m);
-    auto enqueue_iteration = [&](int j) -> hb_status {
-        hb_status e;
-        if ((e = launch_ax(m, lambda, w.p, w.Ap, w.part_ax, w.state, j, s))) return e;
-        if ((e = launch_cg_alpha(w, axg, w.state, j, s))) return e;
-        if ((e = launch_cg_residual(n, w.r, w.Ap, w, w.state, j, s))) return e;
-        if ((e = launch_cg_beta(n, w, w.state, j, s))) return e;
-        return launch_cg_update(n, dev_x, w.p, w.r, w.Ap, w.state, j, s);
-    };
-    auto read_state = [&]() -> hb_status {
-        HB_HIP(hipMemcpyAsync(w.host_state, w.state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    // FP64 iterative refinement around CG with the FP32 operator.
+    const int max_outer = opts->max_outer > 0 ? opts->max_outer : 60;
+    const double eta = opts->inner_rtol > 0.0 ? opts->inner_rtol : 1e-3;
+    const int64_t n = m->NG;
+    if (opts->x0_zero && (st = launch_zero(dev_x, n, s))) return st;
+    double bb = 0.0;
+    {
+        // ||b||: r = b - 0
+        if ((st = launch_zero(w.Ap, n, s)) || (st = launch_residual_norm(n, dev_b, w.Ap, w.rout, w, w.dnorm, s)))
+            return st;
+        HB_HIP(hipMemcpyAsync(w.host_norm, w.dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
         HB_HIP(hipStreamSynchronize(s));
-        return HB_OK;
-    };
-    // Fixed mode enqueues every iteration at once; tolerance mode reads the
-    // device state back every `chunk` iterations to stop launching.
-    const int chunk = opts->fixed_iters ? std::max(opts->max_iter, 1)
-                                        : (opts->check_every > 0 ? opts->check_every : 25);
-    int enqueued = 0;
-    if (!opts->fixed_iters && (st = read_state())) return st;
-    while (enqueued < opts->max_iter && (opts->fixed_iters || w.host_state->done_at > enqueued)) {
-        const int k = std::min(chunk, opts->max_iter - enqueued);
-        for (int i = 0; i < k; ++i)
-            if ((st = enqueue_iteration(enqueued + i))) return st;
-        enqueued += k;
-        if (!opts->fixed_iters && (st = read_state())) return st;
+        bb = *w.host_norm;
     }
-    if ((st = read_state())) return st;
-    const CgState hs = *w.host_state;
-    double rho0 = 0.0, rho_last = 0.0;
-    HB_HIP(hipMemcpy(&rho0, w.rho, sizeof(double), hipMemcpyDeviceToHost));
-    HB_HIP(hipMemcpy(&rho_last, w.rho + hs.iters, sizeof(double), hipMemcpyDeviceToHost));
-    if (host_res_hist) HB_HIP(hipMemcpy(host_res_hist, w.hist, sizeof(double) * (hs.iters + 1), hipMemcpyDeviceToHost));
+    const double bnorm = std::sqrt(bb);
+    if (!std::isfinite(bnorm)) {
+        if (result) {
+            *result = hb_cg_result{};
+            result->status = HB_ERR_NONFINITE;
+        }
+        return HB_ERR_NONFINITE;
+    }
+    int outer = 0, inner_total = 0, fp64_iters = 0;
+    hb_status status = HB_ERR_NOT_CONVERGED;
+    double res = 0.0, res_prev = 0.0, res0 = 0.0;
+    for (;; ++outer) {
+        double rr = 0.0;
+        if ((st = true_residual_sq(m, lambda, dev_b, dev_x, s, &rr))) return st;
+        res = std::sqrt(rr);
+        if (outer == 0) res0 = res;
+        if (host_res_hist && outer <= opts->max_iter) host_res_hist[outer] = res;
+        if (!std::isfinite(res)) {
+            status = outer == 0 ? HB_ERR_NONFINITE : HB_ERR_BREAKDOWN;
+            break;
+        }
+        if (res <= opts->rtol * bnorm) {
+            status = HB_OK;
+            break;
+        }
+        const bool stalled = outer > 0 && res > 0.5 * res_prev;
+        if (stalled) {
+            // The FP32 operator cannot reduce this residual any further: finish
+            // with FP64 CG from the current iterate (true residual computed again below).
+            const int budget = std::max(opts->max_iter - inner_total, 0);
+            if ((st = run_cg<double>(m, lambda, dev_b, dev_x, w.Ap, 0, budget, opts->rtol, opts->check_every, s)))
+                return st;
+            fp64_iters = w.host_state->iters;
+            if ((st = true_residual_sq(m, lambda, dev_b, dev_x, s, &rr))) return st;
+            res = std::sqrt(rr);
+            status = res <= opts->rtol * bnorm ? HB_OK : static_cast<hb_status>(
+                w.host_state->status == HB_OK ? HB_ERR_NOT_CONVERGED : w.host_state->status);
+            break;
+        }
+        if (outer >= max_outer || inner_total >= opts->max_iter) break;
+        res_prev = res;
+        // inner solve A_32 d = r (r = b - A x is in w.rout)
+        if ((st = run_cg<float>(m, lambda, w.rout, w.d, w.Ap32, 1, opts->max_iter - inner_total, eta,
+                                opts->check_every, s)))
+            return st;
+        inner_total += w.host_state->iters;
+        if ((st = launch_axpy(n, dev_x, w.d, s))) return st;
+    }
+    HB_HIP(hipStreamSynchronize(s));
     if (result) {
-        result->iters = hs.iters;
-        result->status = hs.status;
-        result->res0 = std::sqrt(rho0);
-        result->res = std::sqrt(rho_last);
-        result->bnorm = std::sqrt(hs.bb);
+        *result = hb_cg_result{};
+        result->iters = inner_total;
+        result->status = status;
+        result->res0 = res0;
+        result->res = res;
+        result->bnorm = bnorm;
+        result->outer_iters = outer;
+        result->fp64_iters = fp64_iters;
     }
-    return static_cast<hb_status>(hs.status);
+    return status;
 }
 
 hb_status hb_stream_probe(const double *dev_in, double *dev_out, int64_t n, void *stream)

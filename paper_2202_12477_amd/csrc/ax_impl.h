@@ -12,11 +12,15 @@
 //     scalar cache;
 //   - each block holds EPB elements (EPB*(N+1)^2 <= 256 threads), so N=7 is
 //     one wave per element and low orders pack several elements per wave.
-// HBM streams: map (4 B/node) and the 7 geometric values (56 B/node) once,
-// coalesced per layer (G non-temporal, two layers ahead); x through an
-// indirect (cache-friendly) gather; y by device-scope FP64 atomic adds into a
-// zeroed vector (atomics on every node: mixing plain stores into lines that
-// other elements update atomically measured far slower).
+// HBM streams: map (4 B/node) and the 7 geometric values once, coalesced per
+// layer (G non-temporal, two layers ahead); x through an indirect
+// (cache-friendly) gather; y by device-scope atomic adds into a zeroed vector
+// (atomics on every node: mixing plain stores into lines that other elements
+// update atomically measured far slower).
+//
+// T is the arithmetic type: double (the method's FP64 operator) or float (the
+// FP32 operator of the mixed-precision solver: FP32 geometry and D, x rounded
+// to FP32 on load, FP32 accumulation and assembly).  x is FP64 in both.
 #pragma once
 
 #include "common.h"
@@ -31,39 +35,37 @@ struct AxShape {
     static constexpr int np3 = np2 * n1;
     static constexpr int epb = (256 / np2) > 0 ? (256 / np2) : 1;
     static constexpr int threads = (epb * np2 + 63) / 64 * 64;
-    // Registers per thread: 4(N+1) doubles of D (rows and columns a, b), the
-    // t-column of x, f_t and y (3(N+1) doubles), the map column (N+1) and a
-    // layer of G: about 15(N+1)+40 VGPRs.  Ask for the occupancy that fits it,
-    // so the compiler neither spills nor hoists every layer's loads at once.
-    static constexpr int vgprs = (15 * n1 + 40 + 7) / 8 * 8;
-    static constexpr int waves_per_eu = 512 / vgprs < 1 ? 1 : (512 / vgprs > 8 ? 8 : 512 / vgprs);
 };
 
 // Materialise a value here: stops the compiler from sinking a layer's
 // arithmetic to the end of the kernel, which would keep every layer's LDS
 // operands live at once.
-__device__ inline void pin(double &v) { asm volatile("" : "+v"(v)); }
+template <typename T>
+__device__ inline void pin(T &v)
+{
+    asm volatile("" : "+v"(v));
+}
 
-__device__ inline void atomic_add_f64(double *p, double v)
+template <typename T>
+__device__ inline void atomic_add(T *p, T v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int N, bool DOT>
-__global__ __launch_bounds__(AxShape<N>::threads)
-void ax_kernel(
-    int64_t E, const int32_t *__restrict__ map, const double *__restrict__ geo, const double *__restrict__ Dm,
-    double lambda, const double *__restrict__ x, double *__restrict__ y, double *__restrict__ partial,
-    const CgState *__restrict__ st, int j)
+template <int N, bool DOT, typename T>
+__global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
+    int64_t E, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm, T lambda,
+    const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st,
+    int j)
 {
     using S = AxShape<N>;
     constexpr int n1 = S::n1, np2 = S::np2, np3 = S::np3, epb = S::epb;
     if constexpr (DOT) {
         if (st->done_at <= j) return;
     }
-    __shared__ double sq[epb][np2];
-    __shared__ double sr[epb][np2];
-    __shared__ double ss[epb][np2];
+    __shared__ T sq[epb][np2];
+    __shared__ T sr[epb][np2];
+    __shared__ T ss[epb][np2];
     __shared__ double red[S::threads / 64];
 
     const int t = threadIdx.x;
@@ -76,7 +78,7 @@ void ax_kernel(
     const int64_t eo = e < E ? e : E - 1;  // inactive lanes read a valid element and discard it
 
     // rows and columns a, b of D, loaded once and kept in registers
-    double Da[n1], Db[n1], DaT[n1], DbT[n1];
+    T Da[n1], Db[n1], DaT[n1], DbT[n1];
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
         Da[m] = Dm[a * n1 + m];
@@ -87,28 +89,28 @@ void ax_kernel(
 
     // gather through Z: the (a,b) column of the element
     uint32_t idx[n1];
-    double q[n1];
+    T q[n1];
     const uint32_t *me = reinterpret_cast<const uint32_t *>(map) + eo * np3 + ab;
 #pragma unroll
     for (int c = 0; c < n1; ++c) idx[c] = me[c * np2];
 #pragma unroll
-    for (int c = 0; c < n1; ++c) q[c] = x[idx[c]];
+    for (int c = 0; c < n1; ++c) q[c] = static_cast<T>(x[idx[c]]);
 
     // G is streamed once: non-temporal loads keep it from evicting x and y from
     // the caches.  Layers c+1 and c+2 are in flight while layer c is computed.
-    const double *ge = geo + eo * kGeo * np3 + ab;
-    double Gn[kGeo], Gnn[kGeo];
+    const T *ge = geo + eo * kGeo * np3 + ab;
+    T Gn[kGeo], Gnn[kGeo];
 #pragma unroll
     for (int f = 0; f < kGeo; ++f) Gn[f] = __builtin_nontemporal_load(&ge[f * np3]);
 #pragma unroll
     for (int f = 0; f < kGeo; ++f) Gnn[f] = __builtin_nontemporal_load(&ge[f * np3 + np2]);  // n1 >= 2
-    double ft[n1], yv[n1];
+    T ft[n1], yv[n1];
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
         // keep each layer's instructions together: stops the scheduler from
         // hoisting every layer's loads (and spilling them)
         __builtin_amdgcn_sched_barrier(0);
-        double G[kGeo];
+        T G[kGeo];
 #pragma unroll
         for (int f = 0; f < kGeo; ++f) G[f] = Gn[f];
 #pragma unroll
@@ -118,22 +120,22 @@ void ax_kernel(
             for (int f = 0; f < kGeo; ++f) Gnn[f] = __builtin_nontemporal_load(&ge[f * np3 + (c + 2) * np2]);
         }
         // t-derivative from registers; D[c][*] is uniform (scalar loads)
-        double qt = 0.0;
+        T qt = 0;
 #pragma unroll
         for (int m = 0; m < n1; ++m) qt += Dm[c * n1 + m] * q[m];
         if (lane_used) sq[el][ab] = q[c];
         __syncthreads();
-        double qr = 0.0, qs = 0.0;
+        T qr = 0, qs = 0;
 #pragma unroll
         for (int m = 0; m < n1; ++m) {
             qr += Da[m] * sq[el][b * n1 + m];
             qs += Db[m] * sq[el][m * n1 + a];
         }
-        const double fr = G[0] * qr + G[1] * qs + G[2] * qt;
-        const double fs = G[1] * qr + G[3] * qs + G[4] * qt;
+        const T fr = G[0] * qr + G[1] * qs + G[2] * qt;
+        const T fs = G[1] * qr + G[3] * qs + G[4] * qt;
         ft[c] = G[2] * qr + G[4] * qs + G[5] * qt;
         pin(ft[c]);
-        double acc = lambda * G[6] * q[c];
+        T acc = lambda * G[6] * q[c];
         if (lane_used) {
             sr[el][ab] = fr;
             ss[el][ab] = fs;
@@ -148,7 +150,7 @@ void ax_kernel(
     // t-part of D^T from registers
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
-        double s = 0.0;
+        T s = 0;
 #pragma unroll
         for (int m = 0; m < n1; ++m) s += Dm[m * n1 + c] * ft[m];
         yv[c] += s;
@@ -156,13 +158,14 @@ void ax_kernel(
     // assemble through Z^T
     if (active) {
 #pragma unroll
-        for (int c = 0; c < n1; ++c) atomic_add_f64(&y[idx[c]], yv[c]);
+        for (int c = 0; c < n1; ++c) atomic_add(&y[idx[c]], yv[c]);
     }
     if constexpr (DOT) {
+        // sum_e x_e . y_e = x . Z^T y_L = x . A x, accumulated in FP64
         double v = 0.0;
         if (active) {
 #pragma unroll
-            for (int c = 0; c < n1; ++c) v += q[c] * yv[c];
+            for (int c = 0; c < n1; ++c) v += static_cast<double>(q[c]) * static_cast<double>(yv[c]);
         }
         v = block_sum(v, red);
         if (t == 0) partial[blockIdx.x] = v;
@@ -175,20 +178,37 @@ int ax_grid(int64_t E)
     return static_cast<int>((E + AxShape<N>::epb - 1) / AxShape<N>::epb);
 }
 
-template <int N>
-hb_status launch_ax_n(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
-                      int j, hipStream_t s)
+template <int N, typename T>
+hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambda, const double *x, T *y,
+                      double *partial, CgState *st, int j, hipStream_t s)
 {
     const int grid = ax_grid<N>(m->E);
     if (grid == 0) return HB_OK;
+    const T lam = static_cast<T>(lambda);
     if (st)
-        ax_kernel<N, true><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, m->geo, m->D, lambda, x, y, partial, st,
-                                                                j);
+        ax_kernel<N, true, T><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y, partial, st, j);
     else
-        ax_kernel<N, false><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, m->geo, m->D, lambda, x, y, nullptr,
-                                                                 nullptr, 0);
+        ax_kernel<N, false, T><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y, nullptr,
+                                                                    nullptr, 0);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
 }  // namespace hb
+
+// One degree's entry points (FP64 and FP32 operator, grid size), expanded in
+// the per-range translation units so the instantiations compile in parallel.
+#define HB_AX_INSTANCE(n)                                                                                      \
+    namespace hb {                                                                                             \
+    hb_status launch_ax_##n(const hb_mesh_s *m, double l, const double *x, double *y, double *p, CgState *st,  \
+                            int j, hipStream_t s)                                                              \
+    {                                                                                                          \
+        return launch_ax_n<n, double>(m, m->geo, m->D, l, x, y, p, st, j, s);                                  \
+    }                                                                                                          \
+    hb_status launch_ax32_##n(const hb_mesh_s *m, double l, const double *x, float *y, double *p, CgState *st, \
+                              int j, hipStream_t s)                                                            \
+    {                                                                                                          \
+        return launch_ax_n<n, float>(m, m->geo32, m->D32, l, x, y, p, st, j, s);                               \
+    }                                                                                                          \
+    int ax_grid_##n(int64_t E) { return ax_grid<n>(E); }                                                       \
+    }

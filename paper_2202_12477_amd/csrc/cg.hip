@@ -25,10 +25,11 @@ constexpr int kFinThreads = 1024;
 
 __device__ inline bool stopped(const CgState *st, int j) { return st->done_at <= j; }
 
-__global__ __launch_bounds__(kVecThreads) void zero_kernel(double *__restrict__ v, int64_t n)
+template <typename V>
+__global__ __launch_bounds__(kVecThreads) void zero_kernel(V *__restrict__ v, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        v[i] = 0.0;
+        v[i] = V(0);
 }
 
 __global__ void setup_state_kernel(CgState *st, int max_iter, double rtol)
@@ -36,6 +37,7 @@ __global__ void setup_state_kernel(CgState *st, int max_iter, double rtol)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->bb = st->alpha = st->beta = st->pAp = 0.0;
     st->rtol = rtol;
+    st->stop_res = -1.0;
     st->max_iter = max_iter;
     st->done_at = INT_MAX;
     st->iters = 0;
@@ -43,19 +45,20 @@ __global__ void setup_state_kernel(CgState *st, int max_iter, double rtol)
 }
 
 // r0 = b - A x0 (Ap holds A x0 unless x0 = 0), p = r0, Ap = 0; partials of r0.r0 and b.b.
+template <typename TAp>
 __global__ __launch_bounds__(kVecThreads) void init_kernel(int64_t n, const double *__restrict__ b,
                                                           double *__restrict__ x, double *__restrict__ r,
-                                                          double *__restrict__ p, double *__restrict__ Ap,
+                                                          double *__restrict__ p, TAp *__restrict__ Ap,
                                                           int x0_zero, double *__restrict__ partial)
 {
     __shared__ double red[kVecThreads / 64];
     double rr = 0.0, bb = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double bi = b[i];
-        const double ri = x0_zero ? bi : bi - Ap[i];
+        const double ri = x0_zero ? bi : bi - static_cast<double>(Ap[i]);
         r[i] = ri;
         p[i] = ri;
-        Ap[i] = 0.0;
+        Ap[i] = TAp(0);
         if (x0_zero) x[i] = 0.0;
         rr += ri * ri;
         bb += bi * bi;
@@ -79,10 +82,11 @@ __global__ __launch_bounds__(kFinThreads) void init_finish_kernel(const double *
     st->bb = bb;
     rho[0] = rho0;
     hist[0] = sqrt(rho0);
+    st->stop_res = st->rtol >= 0.0 ? st->rtol * sqrt(bb) : -1.0;
     if (!isfinite(rho0)) {
         st->done_at = 0;
         st->status = HB_ERR_NONFINITE;
-    } else if (rho0 == 0.0 || (st->rtol >= 0.0 && sqrt(rho0) <= st->rtol * sqrt(bb))) {
+    } else if (rho0 == 0.0 || sqrt(rho0) <= st->stop_res) {
         st->done_at = 0;  // already solved
     } else if (st->max_iter == 0) {
         st->done_at = 0;
@@ -108,8 +112,9 @@ __global__ __launch_bounds__(kFinThreads) void alpha_kernel(const double *__rest
 }
 
 // r -= alpha Ap; partials of r.r.
+template <typename TAp>
 __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, double *__restrict__ r,
-                                                              const double *__restrict__ Ap,
+                                                              const TAp *__restrict__ Ap,
                                                               double *__restrict__ partial, const CgState *st, int j)
 {
     if (stopped(st, j)) return;
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, double
     const double alpha = st->alpha;
     double rr = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double ri = r[i] - alpha * Ap[i];
+        const double ri = r[i] - alpha * static_cast<double>(Ap[i]);
         r[i] = ri;
         rr += ri * ri;
     }
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restr
     if (!isfinite(rho_new)) {
         st->done_at = j + 1;
         st->status = HB_ERR_BREAKDOWN;
-    } else if (rho_new == 0.0 || (st->rtol >= 0.0 && sqrt(rho_new) <= st->rtol * sqrt(st->bb))) {
+    } else if (rho_new == 0.0 || sqrt(rho_new) <= st->stop_res) {
         st->done_at = j + 1;
         st->status = HB_OK;
     } else if (j + 1 >= st->max_iter) {
@@ -151,8 +156,9 @@ __global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restr
 }
 
 // x += alpha p; p = r + beta p; Ap = 0 (the next operator call assembles into it).
+template <typename TAp>
 __global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *__restrict__ x, double *__restrict__ p,
-                                                            const double *__restrict__ r, double *__restrict__ Ap,
+                                                            const double *__restrict__ r, TAp *__restrict__ Ap,
                                                             const CgState *st, int j)
 {
     if (stopped(st, j)) return;
@@ -161,8 +167,72 @@ __global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *
         const double pi = p[i];
         x[i] += alpha * pi;
         p[i] = r[i] + beta * pi;
-        Ap[i] = 0.0;
+        Ap[i] = TAp(0);
     }
+}
+
+// r = b - t; partials of r.r.
+__global__ __launch_bounds__(kVecThreads) void residual_norm_kernel(int64_t n, const double *__restrict__ b,
+                                                                   const double *__restrict__ t,
+                                                                   double *__restrict__ r,
+                                                                   double *__restrict__ partial)
+{
+    __shared__ double red[kVecThreads / 64];
+    double rr = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double ri = b[i] - t[i];
+        r[i] = ri;
+        rr += ri * ri;
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = rr;
+}
+
+__global__ __launch_bounds__(kFinThreads) void replace_finish_kernel(const double *__restrict__ partial, int nblk,
+                                                                    CgState *st, double *__restrict__ rho,
+                                                                    double *__restrict__ hist, int j,
+                                                                    double *__restrict__ out)
+{
+    __shared__ double red[kFinThreads / 64];
+    const double rr = sum_partials(partial, nblk, red);
+    if (threadIdx.x != 0) return;
+    rho[j] = rr;
+    hist[j] = sqrt(rr);
+    *out = rr;
+    if (!isfinite(rr)) {
+        st->done_at = j;
+        st->status = HB_ERR_BREAKDOWN;
+    }
+}
+
+__global__ void resume_kernel(CgState *st, double stop_res)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->stop_res = stop_res;
+    st->done_at = INT_MAX;
+    st->status = HB_OK;
+}
+
+__global__ __launch_bounds__(kFinThreads) void sum_kernel(const double *__restrict__ partial, int nblk,
+                                                         double *__restrict__ out)
+{
+    __shared__ double red[kFinThreads / 64];
+    const double s = sum_partials(partial, nblk, red);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ __launch_bounds__(kVecThreads) void axpy_kernel(int64_t n, double *__restrict__ x,
+                                                          const double *__restrict__ d)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += d[i];
+}
+
+__global__ __launch_bounds__(kVecThreads) void round_f32_kernel(const double *__restrict__ in, float *__restrict__ out,
+                                                               int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = static_cast<float>(in[i]);  // round to nearest
 }
 
 }  // namespace
@@ -173,13 +243,17 @@ int vec_blocks(int64_t n)
     return static_cast<int>(want < 1 ? 1 : (want > 2048 ? 2048 : want));
 }
 
-hb_status launch_zero(double *v, int64_t n, hipStream_t s)
+template <typename V>
+hb_status zero_any(V *v, int64_t n, hipStream_t s)
 {
     if (n == 0) return HB_OK;
-    zero_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(v, n);
+    zero_kernel<V><<<vec_blocks(n), kVecThreads, 0, s>>>(v, n);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
+
+hb_status launch_zero(double *v, int64_t n, hipStream_t s) { return zero_any(v, n, s); }
+hb_status launch_zero(float *v, int64_t n, hipStream_t s) { return zero_any(v, n, s); }
 
 hb_status launch_cg_setup_state(CgState *st, int max_iter, double rtol, hipStream_t s)
 {
@@ -188,11 +262,12 @@ hb_status launch_cg_setup_state(CgState *st, int max_iter, double rtol, hipStrea
     return HB_OK;
 }
 
-hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p, double *Ap, int x0_zero,
+template <typename TAp>
+hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p, TAp *Ap, int x0_zero,
                          CgWork &w, CgState *st, hipStream_t s)
 {
     const int g = vec_blocks(n);
-    init_kernel<<<g, kVecThreads, 0, s>>>(n, b, x, r, p, Ap, x0_zero, w.part_vec);
+    init_kernel<TAp><<<g, kVecThreads, 0, s>>>(n, b, x, r, p, Ap, x0_zero, w.part_vec);
     init_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, st, w.rho, w.hist);
     HB_HIP(hipGetLastError());
     return HB_OK;
@@ -205,9 +280,10 @@ hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, int j, hipStream_
     return HB_OK;
 }
 
-hb_status launch_cg_residual(int64_t n, double *r, const double *Ap, CgWork &w, CgState *st, int j, hipStream_t s)
+template <typename TAp>
+hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, int j, hipStream_t s)
 {
-    residual_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, w.part_vec, st, j);
+    residual_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, w.part_vec, st, j);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
@@ -219,10 +295,65 @@ hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, int j, hipStream_t s
     return HB_OK;
 }
 
-hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, double *Ap, CgState *st, int j,
+template <typename TAp>
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, int j,
                            hipStream_t s)
 {
-    update_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, st, j);
+    update_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, st, j);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+template hb_status launch_cg_init<double>(int64_t, const double *, double *, double *, double *, double *, int,
+                                          CgWork &, CgState *, hipStream_t);
+template hb_status launch_cg_init<float>(int64_t, const double *, double *, double *, double *, float *, int,
+                                         CgWork &, CgState *, hipStream_t);
+template hb_status launch_cg_residual<double>(int64_t, double *, const double *, CgWork &, CgState *, int,
+                                              hipStream_t);
+template hb_status launch_cg_residual<float>(int64_t, double *, const float *, CgWork &, CgState *, int, hipStream_t);
+template hb_status launch_cg_update<double>(int64_t, double *, double *, const double *, double *, CgState *, int,
+                                            hipStream_t);
+template hb_status launch_cg_update<float>(int64_t, double *, double *, const double *, float *, CgState *, int,
+                                           hipStream_t);
+
+hb_status launch_residual_norm(int64_t n, const double *b, const double *t, double *r, CgWork &w, double *out,
+                               hipStream_t s)
+{
+    const int g = vec_blocks(n);
+    residual_norm_kernel<<<g, kVecThreads, 0, s>>>(n, b, t, r, w.part_vec);
+    sum_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, out);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st, int j,
+                            double *out, hipStream_t s)
+{
+    const int g = vec_blocks(n);
+    residual_norm_kernel<<<g, kVecThreads, 0, s>>>(n, b, t, r, w.part_vec);
+    replace_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, st, w.rho, w.hist, j, out);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_cg_resume(CgState *st, double stop_res, hipStream_t s)
+{
+    resume_kernel<<<1, 64, 0, s>>>(st, stop_res);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_axpy(int64_t n, double *x, const double *d, hipStream_t s)
+{
+    axpy_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, d);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_round_f32(const double *in, float *out, int64_t n, hipStream_t s)
+{
+    if (n == 0) return HB_OK;
+    round_f32_kernel<<<vec_blocks(n), kVecThreads, 0, s>>>(in, out, n);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }

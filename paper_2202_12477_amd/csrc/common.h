@@ -37,6 +37,7 @@ struct CgState {
     double beta;       // beta of the current iteration
     double pAp;        // p . A p of the current iteration
     double rtol;       // < 0 in fixed-iteration mode
+    double stop_res;   // stop once ||r_j|| <= stop_res (< 0: never; set from rtol ||b|| at the start)
     int32_t max_iter;
     int32_t done_at;   // iterations j >= done_at do not run (INT32_MAX while running)
     int32_t iters;     // completed iterations
@@ -52,9 +53,14 @@ struct CgWork {
     double *part_vec = nullptr; // vector-kernel block partials (>= 2 * vector grid)
     int32_t part_ax_len = 0, part_vec_len = 0;
     double *rho = nullptr;      // r_j . r_j, j = 0..max_iter
+    // mixed-precision refinement: outer residual, correction, FP32 operator output
+    double *rout = nullptr, *d = nullptr;
+    float *Ap32 = nullptr;
     double *hist = nullptr;     // ||r_j||, j = 0..max_iter
     CgState *state = nullptr;
+    double *dnorm = nullptr;        // one device scalar (a squared norm)
     CgState *host_state = nullptr;  // pinned mirror for read-back
+    double *host_norm = nullptr;    // pinned mirror of dnorm
     size_t bytes = 0;               // device bytes held (counted in the mesh's device_bytes)
 };
 
@@ -68,6 +74,8 @@ struct hb_mesh_s {
     double *geo = nullptr;    // [E][7][(N+1)^3]
     double *D = nullptr;      // [(N+1)^2] row-major
     double *xi = nullptr, *w = nullptr;  // device copies of the GLL nodes and weights
+    float *geo32 = nullptr;   // FP32 copy of geo (HB_MESH_FP32), rounded once
+    float *D32 = nullptr;     // FP32 copy of D
     double h_xi[hb::kMaxN + 1], h_w[hb::kMaxN + 1], h_D[(hb::kMaxN + 1) * (hb::kMaxN + 1)];
     hb::CgWork cg;
     size_t device_bytes = 0;
@@ -88,19 +96,40 @@ hb_status launch_rhs(int64_t n, uint64_t seed, double *b, hipStream_t s);
 // its share of sum_e x_e . y_e (= x . A x) to partial[block].
 hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
                     int j, hipStream_t s);
+// The FP32 operator (mesh built with HB_MESH_FP32): x FP64, y FP32.
+hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float *y, double *partial, CgState *st,
+                      int j, hipStream_t s);
 int ax_blocks(const hb_mesh_s *m);
 
-// Vector kernels of CG (cg.hip).
+// Vector kernels of CG (cg.hip).  TAp is the type of the operator output Ap
+// (double for the FP64 operator, float for the FP32 one); every other vector
+// and every dot product is FP64.
 int vec_blocks(int64_t n);
 hb_status launch_zero(double *v, int64_t n, hipStream_t s);
+hb_status launch_zero(float *v, int64_t n, hipStream_t s);
 hb_status launch_cg_setup_state(CgState *st, int max_iter, double rtol, hipStream_t s);
-hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p, double *Ap, int x0_zero,
+template <typename TAp>
+hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p, TAp *Ap, int x0_zero,
                          CgWork &w, CgState *st, hipStream_t s);
 hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, int j, hipStream_t s);
-hb_status launch_cg_residual(int64_t n, double *r, const double *Ap, CgWork &w, CgState *st, int j, hipStream_t s);
+template <typename TAp>
+hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, int j, hipStream_t s);
 hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, int j, hipStream_t s);
-hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, double *Ap, CgState *st, int j,
+template <typename TAp>
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, int j,
                            hipStream_t s);
+// Residual replacement at iteration j: r = b - t (t = A x from the FP64
+// operator), rho_j = r.r, history entry j, *out = r.r; then the solve resumes
+// with a new stopping threshold on ||r||.
+hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st, int j,
+                            double *out, hipStream_t s);
+hb_status launch_cg_resume(CgState *st, double stop_res, hipStream_t s);
+// Refinement helpers: r = b - t with ||r||^2 into *out (one block finishes), and x += d.
+hb_status launch_residual_norm(int64_t n, const double *b, const double *t, double *r, CgWork &w, double *out,
+                               hipStream_t s);
+hb_status launch_axpy(int64_t n, double *x, const double *d, hipStream_t s);
+// FP64 -> FP32 rounding of an array (geometry and D of HB_MESH_FP32 meshes).
+hb_status launch_round_f32(const double *in, float *out, int64_t n, hipStream_t s);
 
 // 8:1 streaming probe (stream.hip).
 hb_status launch_stream_probe(const double *in, double *out, int64_t n, hipStream_t s);

@@ -47,13 +47,13 @@ def test_status_strings(L):
 
 
 def _desc(**kw):
-    d = dict(nx=2, ny=2, nz=2, N=3, jitter=0.0, seed=0, mass=0, reserved=0)
+    d = dict(nx=2, ny=2, nz=2, N=3, jitter=0.0, seed=0, mass=0, flags=0)
     d.update(kw)
     return hb._MeshDesc(**d)
 
 
 @pytest.mark.parametrize("bad", [dict(N=0), dict(N=16), dict(nx=0), dict(nz=-1), dict(jitter=0.5),
-                                 dict(jitter=-0.1), dict(jitter=float("nan")), dict(mass=2), dict(reserved=1),
+                                 dict(jitter=-0.1), dict(jitter=float("nan")), dict(mass=2), dict(flags=2),
                                  dict(nx=2000, ny=2000, nz=2000, N=15)])
 def test_mesh_create_rejects_bad_descriptors(L, bad):
     h = ctypes.c_void_p(1234)
@@ -71,8 +71,9 @@ def test_null_arguments(L):
     assert L.hb_mesh_query(None, None) == hb.HB_ERR_INVALID_ARG
     assert L.hb_rhs_uniform(-1, 0, None, None) == hb.HB_ERR_INVALID_ARG
     assert L.hb_stream_probe(None, None, 10, None) == hb.HB_ERR_INVALID_ARG
-    opts = hb._CgOpts(10, 1, 0.0, 1, 0)
+    opts = hb._CgOpts(10, 1, 0.0, 1, 0, 0, 0, 0.0)
     assert L.hb_cg_solve(None, 1.0, None, None, ctypes.byref(opts), None, None, None) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_ax_f32(None, 1.0, None, None, None) == hb.HB_ERR_INVALID_ARG
 
 
 def test_no_device_is_reported(L):
