@@ -103,15 +103,13 @@ hb_status ensure_cg(hb_mesh_s *m, int max_iter, bool mixed)
 }
 
 // The operator for each output type: FP64 operator into double, FP32 into float.
-hb_status apply_op(const hb_mesh_s *m, double l, const double *x, double *y, double *part, CgState *st, int j,
-                   hipStream_t s)
+hb_status apply_op(const hb_mesh_s *m, double l, const double *x, double *y, double *part, CgState *st, hipStream_t s)
 {
-    return launch_ax(m, l, x, y, part, st, j, s);
+    return launch_ax(m, l, x, y, part, st, s);
 }
-hb_status apply_op(const hb_mesh_s *m, double l, const double *x, float *y, double *part, CgState *st, int j,
-                   hipStream_t s)
+hb_status apply_op(const hb_mesh_s *m, double l, const double *x, float *y, double *part, CgState *st, hipStream_t s)
 {
-    return launch_ax32(m, l, x, y, part, st, j, s);
+    return launch_ax32(m, l, x, y, part, st, s);
 }
 
 hb_status read_state(CgWork &w, hipStream_t s)
@@ -121,37 +119,39 @@ hb_status read_state(CgWork &w, hipStream_t s)
     return HB_OK;
 }
 
-// Enqueue CG iterations j0, j0+1, ... with the operator whose output type is
-// TAp until the device state stops the solve or max_iter is reached; the state
-// is left in w.host_state.  rtol < 0 (fixed count) enqueues everything at once;
-// otherwise the state is read back every `check_every` iterations.
+// Enqueue CG iterations with the operator whose output type is TAp until
+// the device state stops the solve or max_iter iterations are complete; the
+// state is left in w.host_state.  Fixed mode (every iteration runs) enqueues
+// everything at once; otherwise the state is read back every `check_every`
+// iterations.
 template <typename TAp>
-hb_status cg_iterate(hb_mesh_s *m, double lambda, double *x, TAp *Ap, int j0, int max_iter, bool fixed,
-                     int check_every, hipStream_t s)
+hb_status cg_iterate(hb_mesh_s *m, double lambda, double *x, TAp *Ap, int max_iter, bool fixed, int check_every,
+                     hipStream_t s)
 {
     CgWork &w = m->cg;
     const int64_t n = m->NG;
     const int axg = ax_blocks(m);
     hb_status st;
-    auto enqueue_iteration = [&](int j) -> hb_status {
+    auto enqueue_iteration = [&]() -> hb_status {
         hb_status e;
-        if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, j, s))) return e;
-        if ((e = launch_cg_alpha(w, axg, w.state, j, s))) return e;
-        if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, j, s))) return e;
-        if ((e = launch_cg_beta(n, w, w.state, j, s))) return e;
-        return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.state, j, s);
+        if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, s))) return e;
+        if ((e = launch_cg_alpha(w, axg, w.state, s))) return e;
+        if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, s))) return e;
+        if ((e = launch_cg_beta(n, w, w.state, s))) return e;
+        return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.state, s);
     };
-    const int chunk = fixed ? std::max(max_iter - j0, 1) : (check_every > 0 ? check_every : 25);
-    int enqueued = j0;
-    if (!fixed && (st = read_state(w, s))) return st;
-    while (enqueued < max_iter && (fixed || w.host_state->done_at > enqueued)) {
-        const int k = std::min(chunk, max_iter - enqueued);
+    if ((st = read_state(w, s))) return st;
+    int done_iters = w.host_state->iters;
+    auto stopped = [&]() { return w.host_state->done || w.host_state->pending; };
+    const int chunk = fixed ? std::max(max_iter - done_iters, 1) : (check_every > 0 ? check_every : 25);
+    while (done_iters < max_iter && !stopped()) {
+        const int k = std::min(chunk, max_iter - done_iters);
         for (int i = 0; i < k; ++i)
-            if ((st = enqueue_iteration(enqueued + i))) return st;
-        enqueued += k;
-        if (!fixed && (st = read_state(w, s))) return st;
+            if ((st = enqueue_iteration())) return st;
+        if ((st = read_state(w, s))) return st;
+        done_iters = w.host_state->iters;
     }
-    return read_state(w, s);
+    return HB_OK;
 }
 
 // Algorithm 1: r0 = b - A x0, p = r0, then iterations until the stop test.
@@ -164,10 +164,10 @@ hb_status run_cg(hb_mesh_s *m, double lambda, const double *b, double *x, TAp *A
     hb_status st;
     if ((st = launch_cg_setup_state(w.state, max_iter, rtol, s))) return st;
     if (!x0_zero) {
-        if ((st = launch_zero(Ap, n, s)) || (st = apply_op(m, lambda, x, Ap, nullptr, nullptr, 0, s))) return st;
+        if ((st = launch_zero(Ap, n, s)) || (st = apply_op(m, lambda, x, Ap, nullptr, nullptr, s))) return st;
     }
     if ((st = launch_cg_init<TAp>(n, b, x, w.r, w.p, Ap, x0_zero, w, w.state, s))) return st;
-    return cg_iterate<TAp>(m, lambda, x, Ap, 0, max_iter, rtol < 0.0, check_every, s);
+    return cg_iterate<TAp>(m, lambda, x, Ap, max_iter, rtol < 0.0, check_every, s);
 }
 
 // ||b - A x||^2 with the FP64 operator (t = A x in w.Ap, r = b - t in w.rout).
@@ -175,7 +175,7 @@ hb_status true_residual_sq(hb_mesh_s *m, double lambda, const double *b, const d
 {
     CgWork &w = m->cg;
     hb_status st;
-    if ((st = launch_zero(w.Ap, m->NG, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, 0, s)) ||
+    if ((st = launch_zero(w.Ap, m->NG, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, s)) ||
         (st = launch_residual_norm(m->NG, b, w.Ap, w.rout, w, w.dnorm, s)))
         return st;
     HB_HIP(hipMemcpyAsync(w.host_norm, w.dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -208,7 +208,7 @@ hb_status solve_replace(hb_mesh_s *m, double lambda, const double *b, double *x,
     hb_status st;
     if ((st = launch_cg_setup_state(w.state, opts->max_iter, opts->rtol, s))) return st;
     if (!opts->x0_zero) {
-        if ((st = launch_zero(w.Ap, n, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, 0, s))) return st;
+        if ((st = launch_zero(w.Ap, n, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, s))) return st;
     }
     if ((st = launch_cg_init<double>(n, b, x, w.r, w.p, w.Ap, opts->x0_zero, w, w.state, s)) ||
         (st = launch_zero(w.Ap32, n, s)) || (st = read_state(w, s)))
@@ -222,12 +222,12 @@ hb_status solve_replace(hb_mesh_s *m, double lambda, const double *b, double *x,
     int j = 0, outer = 0, fp64_from = -1;
     hb_status status = static_cast<hb_status>(w.host_state->status);
     bool use32 = true;
-    if (w.host_state->done_at > 0) {
+    if (!w.host_state->done) {
         status = HB_ERR_NOT_CONVERGED;
         if ((st = launch_cg_resume(w.state, std::max(eta * ref, opts->rtol * bnorm), s))) return st;
         for (;;) {
-            st = use32 ? cg_iterate<float>(m, lambda, x, w.Ap32, j, opts->max_iter, false, opts->check_every, s)
-                       : cg_iterate<double>(m, lambda, x, w.Ap, j, opts->max_iter, false, opts->check_every, s);
+            st = use32 ? cg_iterate<float>(m, lambda, x, w.Ap32, opts->max_iter, false, opts->check_every, s)
+                       : cg_iterate<double>(m, lambda, x, w.Ap, opts->max_iter, false, opts->check_every, s);
             if (st) return st;
             j = w.host_state->iters;
             const bool breakdown = w.host_state->status == HB_ERR_BREAKDOWN;
@@ -237,8 +237,8 @@ hb_status solve_replace(hb_mesh_s *m, double lambda, const double *b, double *x,
             }
             // replacement: r = b - A x with the FP64 operator
             double rr = 0.0;
-            if ((st = launch_zero(w.Ap, n, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, 0, s)) ||
-                (st = launch_cg_replace(n, b, w.Ap, w.r, w, w.state, j, w.dnorm, s)) || (st = read_norm(w, s, &rr)))
+            if ((st = launch_zero(w.Ap, n, s)) || (st = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, s)) ||
+                (st = launch_cg_replace(n, b, w.Ap, w.r, w, w.state, w.dnorm, s)) || (st = read_norm(w, s, &rr)))
                 return st;
             ++outer;
             res = std::sqrt(rr);
@@ -429,7 +429,7 @@ hb_status hb_ax(hb_mesh m, double lambda, const double *dev_x, double *dev_y, vo
     hipStream_t s = static_cast<hipStream_t>(stream);
     hb_status st = launch_zero(dev_y, m->NG, s);
     if (st) return st;
-    return launch_ax(m, lambda, dev_x, dev_y, nullptr, nullptr, 0, s);
+    return launch_ax(m, lambda, dev_x, dev_y, nullptr, nullptr, s);
 }
 
 hb_status hb_ax_add(hb_mesh m, double lambda, const double *dev_x, double *dev_y, void *stream)
@@ -437,7 +437,7 @@ hb_status hb_ax_add(hb_mesh m, double lambda, const double *dev_x, double *dev_y
     if (!m || !dev_x || !dev_y) return fail(HB_ERR_INVALID_ARG, "hb_ax_add: null argument");
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(HB_ERR_INVALID_ARG, "hb_ax_add: lambda must be finite and > 0");
     if (dev_x == dev_y) return fail(HB_ERR_INVALID_ARG, "hb_ax_add: x and y must not alias");
-    return launch_ax(m, lambda, dev_x, dev_y, nullptr, nullptr, 0, static_cast<hipStream_t>(stream));
+    return launch_ax(m, lambda, dev_x, dev_y, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
 hb_status hb_ax_f32(hb_mesh m, double lambda, const double *dev_x, float *dev_y, void *stream)
@@ -450,7 +450,7 @@ hb_status hb_ax_f32(hb_mesh m, double lambda, const double *dev_x, float *dev_y,
     hipStream_t s = static_cast<hipStream_t>(stream);
     hb_status st = launch_zero(dev_y, m->NG, s);
     if (st) return st;
-    return launch_ax32(m, lambda, dev_x, dev_y, nullptr, nullptr, 0, s);
+    return launch_ax32(m, lambda, dev_x, dev_y, nullptr, nullptr, s);
 }
 
 hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev_x, const hb_cg_opts *opts,

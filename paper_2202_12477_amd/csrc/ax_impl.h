@@ -55,13 +55,12 @@ __device__ inline void atomic_add(T *p, T v)
 template <int N, bool DOT, typename T>
 __global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
     int64_t E, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm, T lambda,
-    const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st,
-    int j)
+    const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st)
 {
     using S = AxShape<N>;
     constexpr int n1 = S::n1, np2 = S::np2, np3 = S::np3, epb = S::epb;
     if constexpr (DOT) {
-        if (st->done_at <= j) return;
+        if (st->done) return;
     }
     __shared__ T sq[epb][np2];
     __shared__ T sr[epb][np2];
@@ -180,16 +179,16 @@ int ax_grid(int64_t E)
 
 template <int N, typename T>
 hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambda, const double *x, T *y,
-                      double *partial, CgState *st, int j, hipStream_t s)
+                      double *partial, CgState *st, hipStream_t s)
 {
     const int grid = ax_grid<N>(m->E);
     if (grid == 0) return HB_OK;
     const T lam = static_cast<T>(lambda);
     if (st)
-        ax_kernel<N, true, T><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y, partial, st, j);
+        ax_kernel<N, true, T><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y, partial, st);
     else
         ax_kernel<N, false, T><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y, nullptr,
-                                                                    nullptr, 0);
+                                                                    nullptr);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
@@ -201,14 +200,14 @@ hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambd
 #define HB_AX_INSTANCE(n)                                                                                      \
     namespace hb {                                                                                             \
     hb_status launch_ax_##n(const hb_mesh_s *m, double l, const double *x, double *y, double *p, CgState *st,  \
-                            int j, hipStream_t s)                                                              \
+                            hipStream_t s)                                                                     \
     {                                                                                                          \
-        return launch_ax_n<n, double>(m, m->geo, m->D, l, x, y, p, st, j, s);                                  \
+        return launch_ax_n<n, double>(m, m->geo, m->D, l, x, y, p, st, s);                                     \
     }                                                                                                          \
     hb_status launch_ax32_##n(const hb_mesh_s *m, double l, const double *x, float *y, double *p, CgState *st, \
-                              int j, hipStream_t s)                                                            \
+                              hipStream_t s)                                                                   \
     {                                                                                                          \
-        return launch_ax_n<n, float>(m, m->geo32, m->D32, l, x, y, p, st, j, s);                               \
+        return launch_ax_n<n, float>(m, m->geo32, m->D32, l, x, y, p, st, s);                                  \
     }                                                                                                          \
     int ax_grid_##n(int64_t E) { return ax_grid<n>(E); }                                                       \
     }

@@ -2,9 +2,10 @@
 // Conjugate gradient Iteration section, with every scalar kept on the device so
 // the host never waits inside an iteration).
 //
-// Iteration j is five launches on one stream:
+// An iteration is five launches on one stream, identical for every iteration
+// (the iteration number lives in the device state):
 //   operator  Ap = A p, block partials of p.Ap              (ax*.hip)
-//   alpha     one block: p.Ap from the partials, alpha = rho_j / p.Ap
+//   alpha     one block: j = it + 1, p.Ap from the partials, alpha = rho_j / p.Ap
 //   residual  r -= alpha Ap, block partials of r.r
 //   beta      one block: rho_{j+1} = r.r, beta = rho_{j+1} / rho_j, history, stop test
 //   update    x += alpha p; p = r + beta p; Ap = 0 for the next assembly
@@ -23,7 +24,6 @@ namespace {
 constexpr int kVecThreads = 256;
 constexpr int kFinThreads = 1024;
 
-__device__ inline bool stopped(const CgState *st, int j) { return st->done_at <= j; }
 
 template <typename V>
 __global__ __launch_bounds__(kVecThreads) void zero_kernel(V *__restrict__ v, int64_t n)
@@ -39,8 +39,10 @@ __global__ void setup_state_kernel(CgState *st, int max_iter, double rtol)
     st->rtol = rtol;
     st->stop_res = -1.0;
     st->max_iter = max_iter;
-    st->done_at = INT_MAX;
+    st->it = -1;
     st->iters = 0;
+    st->done = 0;
+    st->pending = 0;
     st->status = HB_OK;
 }
 
@@ -84,27 +86,34 @@ __global__ __launch_bounds__(kFinThreads) void init_finish_kernel(const double *
     hist[0] = sqrt(rho0);
     st->stop_res = st->rtol >= 0.0 ? st->rtol * sqrt(bb) : -1.0;
     if (!isfinite(rho0)) {
-        st->done_at = 0;
+        st->done = 1;
         st->status = HB_ERR_NONFINITE;
     } else if (rho0 == 0.0 || sqrt(rho0) <= st->stop_res) {
-        st->done_at = 0;  // already solved
+        st->done = 1;  // already solved
     } else if (st->max_iter == 0) {
-        st->done_at = 0;
+        st->done = 1;
         st->status = st->rtol >= 0.0 ? HB_ERR_NOT_CONVERGED : HB_OK;
     }
 }
 
-// alpha = rho_j / p.Ap, or stop on breakdown (p.Ap <= 0 or not finite).
+// Start of iteration j = it + 1: alpha = rho_j / p.Ap, or stop on breakdown
+// (p.Ap <= 0 or not finite), or apply a stop decided by the previous beta.
 __global__ __launch_bounds__(kFinThreads) void alpha_kernel(const double *__restrict__ partial, int nblk, CgState *st,
-                                                           const double *__restrict__ rho, int j)
+                                                           const double *__restrict__ rho)
 {
-    if (stopped(st, j)) return;
+    if (st->done) return;
+    if (st->pending) {
+        if (threadIdx.x == 0) st->done = 1;
+        return;
+    }
     __shared__ double red[kFinThreads / 64];
     const double pAp = sum_partials(partial, nblk, red);
     if (threadIdx.x != 0) return;
+    const int j = st->it + 1;
+    st->it = j;
     st->pAp = pAp;
     if (!(pAp > 0.0) || !isfinite(pAp)) {
-        st->done_at = j;
+        st->done = 1;
         st->status = HB_ERR_BREAKDOWN;
     } else {
         st->alpha = rho[j] / pAp;
@@ -115,9 +124,9 @@ __global__ __launch_bounds__(kFinThreads) void alpha_kernel(const double *__rest
 template <typename TAp>
 __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, double *__restrict__ r,
                                                               const TAp *__restrict__ Ap,
-                                                              double *__restrict__ partial, const CgState *st, int j)
+                                                              double *__restrict__ partial, const CgState *st)
 {
-    if (stopped(st, j)) return;
+    if (st->done) return;
     __shared__ double red[kVecThreads / 64];
     const double alpha = st->alpha;
     double rr = 0.0;
@@ -132,25 +141,26 @@ __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, double
 
 // rho_{j+1} = r.r, beta, history, convergence / iteration-cap test.
 __global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restrict__ partial, int nblk, CgState *st,
-                                                          double *__restrict__ rho, double *__restrict__ hist, int j)
+                                                          double *__restrict__ rho, double *__restrict__ hist)
 {
-    if (stopped(st, j)) return;
+    if (st->done) return;
     __shared__ double red[kFinThreads / 64];
     const double rho_new = sum_partials(partial, nblk, red);
     if (threadIdx.x != 0) return;
+    const int j = st->it;
     st->beta = rho_new / rho[j];
     rho[j + 1] = rho_new;
     hist[j + 1] = sqrt(rho_new);
     st->iters = j + 1;
-    // this iteration's update still runs (it tests done_at <= j); later ones do not
+    // this iteration's update still runs; the next alpha turns pending into done
     if (!isfinite(rho_new)) {
-        st->done_at = j + 1;
+        st->pending = 1;
         st->status = HB_ERR_BREAKDOWN;
     } else if (rho_new == 0.0 || sqrt(rho_new) <= st->stop_res) {
-        st->done_at = j + 1;
+        st->pending = 1;
         st->status = HB_OK;
     } else if (j + 1 >= st->max_iter) {
-        st->done_at = j + 1;
+        st->pending = 1;
         st->status = st->rtol >= 0.0 ? HB_ERR_NOT_CONVERGED : HB_OK;
     }
 }
@@ -159,9 +169,9 @@ __global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restr
 template <typename TAp>
 __global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *__restrict__ x, double *__restrict__ p,
                                                             const double *__restrict__ r, TAp *__restrict__ Ap,
-                                                            const CgState *st, int j)
+                                                            const CgState *st)
 {
-    if (stopped(st, j)) return;
+    if (st->done) return;
     const double alpha = st->alpha, beta = st->beta;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double pi = p[i];
@@ -190,26 +200,26 @@ __global__ __launch_bounds__(kVecThreads) void residual_norm_kernel(int64_t n, c
 
 __global__ __launch_bounds__(kFinThreads) void replace_finish_kernel(const double *__restrict__ partial, int nblk,
                                                                     CgState *st, double *__restrict__ rho,
-                                                                    double *__restrict__ hist, int j,
+                                                                    double *__restrict__ hist,
                                                                     double *__restrict__ out)
 {
     __shared__ double red[kFinThreads / 64];
     const double rr = sum_partials(partial, nblk, red);
     if (threadIdx.x != 0) return;
+    const int j = st->iters;
     rho[j] = rr;
     hist[j] = sqrt(rr);
     *out = rr;
-    if (!isfinite(rr)) {
-        st->done_at = j;
-        st->status = HB_ERR_BREAKDOWN;
-    }
 }
 
+// Continue after a residual replacement: the next alpha starts iteration `iters`.
 __global__ void resume_kernel(CgState *st, double stop_res)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->stop_res = stop_res;
-    st->done_at = INT_MAX;
+    st->it = st->iters - 1;
+    st->done = 0;
+    st->pending = 0;
     st->status = HB_OK;
 }
 
@@ -273,33 +283,32 @@ hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, doubl
     return HB_OK;
 }
 
-hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, int j, hipStream_t s)
+hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, hipStream_t s)
 {
-    alpha_kernel<<<1, kFinThreads, 0, s>>>(w.part_ax, ax_grid, st, w.rho, j);
+    alpha_kernel<<<1, kFinThreads, 0, s>>>(w.part_ax, ax_grid, st, w.rho);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
 template <typename TAp>
-hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, int j, hipStream_t s)
+hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, hipStream_t s)
 {
-    residual_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, w.part_vec, st, j);
+    residual_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, w.part_vec, st);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
-hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, int j, hipStream_t s)
+hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, hipStream_t s)
 {
-    beta_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, vec_blocks(n), st, w.rho, w.hist, j);
+    beta_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, vec_blocks(n), st, w.rho, w.hist);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
 template <typename TAp>
-hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, int j,
-                           hipStream_t s)
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, hipStream_t s)
 {
-    update_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, st, j);
+    update_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, st);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
@@ -308,12 +317,11 @@ template hb_status launch_cg_init<double>(int64_t, const double *, double *, dou
                                           CgWork &, CgState *, hipStream_t);
 template hb_status launch_cg_init<float>(int64_t, const double *, double *, double *, double *, float *, int,
                                          CgWork &, CgState *, hipStream_t);
-template hb_status launch_cg_residual<double>(int64_t, double *, const double *, CgWork &, CgState *, int,
-                                              hipStream_t);
-template hb_status launch_cg_residual<float>(int64_t, double *, const float *, CgWork &, CgState *, int, hipStream_t);
-template hb_status launch_cg_update<double>(int64_t, double *, double *, const double *, double *, CgState *, int,
+template hb_status launch_cg_residual<double>(int64_t, double *, const double *, CgWork &, CgState *, hipStream_t);
+template hb_status launch_cg_residual<float>(int64_t, double *, const float *, CgWork &, CgState *, hipStream_t);
+template hb_status launch_cg_update<double>(int64_t, double *, double *, const double *, double *, CgState *,
                                             hipStream_t);
-template hb_status launch_cg_update<float>(int64_t, double *, double *, const double *, float *, CgState *, int,
+template hb_status launch_cg_update<float>(int64_t, double *, double *, const double *, float *, CgState *,
                                            hipStream_t);
 
 hb_status launch_residual_norm(int64_t n, const double *b, const double *t, double *r, CgWork &w, double *out,
@@ -326,12 +334,12 @@ hb_status launch_residual_norm(int64_t n, const double *b, const double *t, doub
     return HB_OK;
 }
 
-hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st, int j,
+hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st,
                             double *out, hipStream_t s)
 {
     const int g = vec_blocks(n);
     residual_norm_kernel<<<g, kVecThreads, 0, s>>>(n, b, t, r, w.part_vec);
-    replace_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, st, w.rho, w.hist, j, out);
+    replace_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, st, w.rho, w.hist, out);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }

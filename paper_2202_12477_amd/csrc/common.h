@@ -27,10 +27,16 @@ hb_status hip_fail(hipError_t err, const char *what);
     } while (0)
 
 // Device-resident state of one CG solve (Algorithm 1).  Scalars never leave
-// the device.  Every launch of iteration j receives j and returns at once when
-// done_at <= j, so a fixed sequence of launches can run past convergence
-// harmlessly.  Each field is written only by a single-block kernel and read by
-// later kernels, so no kernel reads what it writes.
+// the device and no kernel takes the iteration number as an argument, so one
+// captured iteration can be replayed and problems at different iterations can
+// share launches.  Fields are written only by single-block kernels and read by
+// later kernels:
+//   alpha (first single-block kernel of an iteration): turns `pending` into
+//     `done`, else advances `it` and computes alpha (or sets `done` on breakdown);
+//   beta: records rho_{it+1}, beta, the history and `iters`; a stop decided
+//     here only sets `pending`, so this iteration's update still runs.
+// Every streaming kernel returns at once when `done` is set (an operator call
+// issued after `pending` was set is wasted but harmless: it touches only Ap).
 struct CgState {
     double bb;         // b . b
     double alpha;      // alpha of the current iteration
@@ -39,8 +45,10 @@ struct CgState {
     double rtol;       // < 0 in fixed-iteration mode
     double stop_res;   // stop once ||r_j|| <= stop_res (< 0: never; set from rtol ||b|| at the start)
     int32_t max_iter;
-    int32_t done_at;   // iterations j >= done_at do not run (INT32_MAX while running)
+    int32_t it;        // index of the current iteration (-1 before the first)
     int32_t iters;     // completed iterations
+    int32_t done;      // no further kernel of this solve does anything
+    int32_t pending;   // stop after the current iteration's update
     int32_t status;    // hb_status of the solve
 };
 
@@ -91,14 +99,14 @@ hb_status build_geometry(hb_mesh_s *m, hipStream_t s);
 hb_status launch_rhs(int64_t n, uint64_t seed, double *b, hipStream_t s);
 
 // Operator (ax*.hip).  y += A x (y is assembled by atomic addition, so a
-// fresh result needs y = 0 first).  With st != nullptr this is iteration j of
-// CG: it returns at once if the solve has stopped, and each block also writes
-// its share of sum_e x_e . y_e (= x . A x) to partial[block].
+// fresh result needs y = 0 first).  With st != nullptr this is the operator
+// step of CG: it returns at once if the solve is done, and each block also
+// writes its share of sum_e x_e . y_e (= x . A x) to partial[block].
 hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
-                    int j, hipStream_t s);
+                    hipStream_t s);
 // The FP32 operator (mesh built with HB_MESH_FP32): x FP64, y FP32.
 hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float *y, double *partial, CgState *st,
-                      int j, hipStream_t s);
+                      hipStream_t s);
 int ax_blocks(const hb_mesh_s *m);
 
 // Vector kernels of CG (cg.hip).  TAp is the type of the operator output Ap
@@ -111,17 +119,16 @@ hb_status launch_cg_setup_state(CgState *st, int max_iter, double rtol, hipStrea
 template <typename TAp>
 hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, double *p, TAp *Ap, int x0_zero,
                          CgWork &w, CgState *st, hipStream_t s);
-hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, int j, hipStream_t s);
+hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, hipStream_t s);
 template <typename TAp>
-hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, int j, hipStream_t s);
-hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, int j, hipStream_t s);
+hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, hipStream_t s);
+hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, hipStream_t s);
 template <typename TAp>
-hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, int j,
-                           hipStream_t s);
-// Residual replacement at iteration j: r = b - t (t = A x from the FP64
-// operator), rho_j = r.r, history entry j, *out = r.r; then the solve resumes
-// with a new stopping threshold on ||r||.
-hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st, int j,
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, hipStream_t s);
+// Residual replacement after the completed iterations: r = b - t (t = A x
+// from the FP64 operator), rho_iters = r.r, history entry iters, *out = r.r;
+// then the solve resumes with a new stopping threshold on ||r||.
+hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st,
                             double *out, hipStream_t s);
 hb_status launch_cg_resume(CgState *st, double stop_res, hipStream_t s);
 // Refinement helpers: r = b - t with ||r||^2 into *out (one block finishes), and x += d.
