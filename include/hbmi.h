@@ -198,6 +198,21 @@ typedef struct {
 hb_status hb_cg_solve(hb_mesh mesh, double lambda, const double *dev_b, double *dev_x, const hb_cg_opts *opts,
                       hb_cg_result *result, double *host_res_hist, void *stream);
 
+/* Batched solve of independent problems (each its own mesh, lambda, b, x):
+ * every problem runs the same algorithm as hb_cg_solve (HB_PREC_FP64, fixed
+ * count or tolerance; or HB_PREC_FP32_RR), but all problems advance together:
+ * an iteration is one operator launch per (degree, precision) class over a
+ * work list of (problem, element tile), then one launch each for the alpha,
+ * residual, beta and update steps of all problems.  Each problem has its own
+ * device state, so problems that stop early simply drop out of the work lists
+ * at the next read-back (every opts->check_every iterations, default 25).
+ * meshes[i] must be distinct (the CG workspace belongs to the mesh).
+ * results[i] is filled for every problem; the return value is HB_OK if all
+ * problems succeeded, else the status of the first that did not.
+ * HB_PREC_FP32_IR is not available here.  Synchronises `stream`. */
+hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lambdas, const double *const *dev_b,
+                         double *const *dev_x, const hb_cg_opts *opts, hb_cg_result *results, void *stream);
+
 /* Empirical streaming probe of the Computational Tests section: every thread
  * reads 8 FP64 values and writes one (8:1 read:write), dev_out[i] =
  * sum_k dev_in[k*n + i], k = 0..7.  dev_in: 8n doubles, dev_out: n doubles.

@@ -68,3 +68,13 @@ ORDER_SWEEP = [order_sweep_case(N) for N in range(1, 16)]
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Standard-normal FP64 vector from numpy's PCG64 stream `seed` (host memory)."""
     return np.random.default_rng(seed).standard_normal(n)
+
+
+def batched_cases(count: int = 64, master_seed: int = 4) -> list:
+    """Uneven independent problems: cubic grids n ~ U{2..24}, N ~ U{3,5,7,9}, each with
+    its own jitter seed and forcing seed, lambda = 1 (drawn from numpy's PCG64 stream)."""
+    rng = np.random.default_rng(master_seed)
+    ns = rng.integers(2, 25, size=count)
+    Ns = rng.choice([3, 5, 7, 9], size=count)
+    return [BoxCase(f"batch{master_seed}_{i}_n{int(n)}_N{int(N)}", int(n), int(n), int(n), int(N), 0.05,
+                    1000 * master_seed + i, 2000 * master_seed + i) for i, (n, N) in enumerate(zip(ns, Ns))]

@@ -35,7 +35,8 @@ PREC_FP32_RR = 2
 # Every entry point of include/hbmi.h, in declaration order.
 EXPORTS = (
     "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax",
-    "hb_ax_add", "hb_ax_f32", "hb_cg_solve", "hb_stream_probe", "hb_status_string", "hb_last_error",
+    "hb_ax_add", "hb_ax_f32", "hb_cg_solve", "hb_batch_solve", "hb_stream_probe", "hb_status_string",
+    "hb_last_error",
 )
 
 
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
         "hb_ax_add": [vp, f64, vp, vp, vp],
         "hb_ax_f32": [vp, f64, vp, vp, vp],
         "hb_cg_solve": [vp, f64, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp, vp],
+        "hb_batch_solve": [i32, vp, vp, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp],
         "hb_stream_probe": [vp, vp, i64, vp],
     }
     for name, args in sig.items():
@@ -247,6 +249,30 @@ class Mesh:
             k = res.outer_iters if prec != PREC_FP64 else res.iters
             out.history = list(hist[: min(k, max_iter) + 1])
         return out
+
+
+def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool = False, rtol: float = 1e-8,
+                x0_zero: bool = True, check_every: int = 0, prec: int = PREC_FP64, inner_rtol: float = 0.0,
+                stream=None, raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
+    """Solve independent problems together (hb_batch_solve); returns (status, [CgResult])."""
+    import torch
+
+    n = len(meshes)
+    if not (len(lams) == len(bs) == len(xs) == n):
+        raise ValueError("one lambda, b and x per mesh")
+    for m, b, x in zip(meshes, bs, xs):
+        if b.numel() != m.NG or x.numel() != m.NG:
+            raise ValueError("vectors must have N_G entries")
+    H = (ctypes.c_void_p * n)(*[m.handle.value for m in meshes])
+    L = (ctypes.c_double * n)(*lams)
+    B = (ctypes.c_void_p * n)(*[_ptr(b, torch.float64) for b in bs])
+    X = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64) for x in xs])
+    R = (_CgResult * n)()
+    opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, 0, inner_rtol)
+    st = lib().hb_batch_solve(n, H, L, B, X, ctypes.byref(opts), R, _stream(stream))
+    if st in raise_on:
+        _check(st, "hb_batch_solve")
+    return st, [CgResult(r.iters, r.status, r.res0, r.res, r.bnorm, r.outer_iters, r.fp64_iters) for r in R]
 
 
 def rhs_uniform(b, seed: int, stream=None):

@@ -28,6 +28,19 @@
 
 namespace hb {
 
+// Pointers into device (global) memory.  The tile routine takes them in the
+// global address space explicitly: callers that read pointers from a table in
+// memory would otherwise hand the compiler generic pointers, and every access
+// would become a flat access (which also waits on the LDS counter).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ inline gptr<T> to_global(T *p)
+{
+    return (gptr<T>)p;
+}
+
 template <int N>
 struct AxShape {
     static constexpr int n1 = N + 1;
@@ -47,21 +60,22 @@ __device__ inline void pin(T &v)
 }
 
 template <typename T>
-__device__ inline void atomic_add(T *p, T v)
+__device__ inline void atomic_add(gptr<T> p, T v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One tile of EPB elements starting at element tile*EPB: y += A x on them and,
+// with DOT, this block's sum of x_e . y_e written to *dot_out (thread 0).
+// Every thread of the block must call it (it synchronises the block).
 template <int N, bool DOT, typename T>
-__global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
-    int64_t E, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm, T lambda,
-    const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st)
+__device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
+                               gptr<const T> __restrict__ geo, gptr<const T> __restrict__ Dm, T lambda,
+                               gptr<const double> __restrict__ x, gptr<T> __restrict__ y,
+                               gptr<double> __restrict__ dot_out)
 {
     using S = AxShape<N>;
     constexpr int n1 = S::n1, np2 = S::np2, np3 = S::np3, epb = S::epb;
-    if constexpr (DOT) {
-        if (st->done) return;
-    }
     __shared__ T sq[epb][np2];
     __shared__ T sr[epb][np2];
     __shared__ T ss[epb][np2];
@@ -72,10 +86,9 @@ __global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
     const int el = lane_used ? t / np2 : epb - 1;  // spare lanes mirror the last element, inactive
     const int ab = lane_used ? t - el * np2 : 0;
     const int a = ab % n1, b = ab / n1;
-    const int64_t e = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * epb + el;
+    const int64_t e = tile * epb + el;
     const bool active = lane_used && (e < E);
     const int64_t eo = e < E ? e : E - 1;  // inactive lanes read a valid element and discard it
-
     // rows and columns a, b of D, loaded once and kept in registers
     T Da[n1], Db[n1], DaT[n1], DbT[n1];
 #pragma unroll
@@ -89,7 +102,7 @@ __global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
     // gather through Z: the (a,b) column of the element
     uint32_t idx[n1];
     T q[n1];
-    const uint32_t *me = reinterpret_cast<const uint32_t *>(map) + eo * np3 + ab;
+    gptr<const uint32_t> me = (gptr<const uint32_t>)map + eo * np3 + ab;
 #pragma unroll
     for (int c = 0; c < n1; ++c) idx[c] = me[c * np2];
 #pragma unroll
@@ -97,7 +110,7 @@ __global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
 
     // G is streamed once: non-temporal loads keep it from evicting x and y from
     // the caches.  Layers c+1 and c+2 are in flight while layer c is computed.
-    const T *ge = geo + eo * kGeo * np3 + ab;
+    gptr<const T> ge = geo + eo * kGeo * np3 + ab;
     T Gn[kGeo], Gnn[kGeo];
 #pragma unroll
     for (int f = 0; f < kGeo; ++f) Gn[f] = __builtin_nontemporal_load(&ge[f * np3]);
@@ -167,8 +180,20 @@ __global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
             for (int c = 0; c < n1; ++c) v += static_cast<double>(q[c]) * static_cast<double>(yv[c]);
         }
         v = block_sum(v, red);
-        if (t == 0) partial[blockIdx.x] = v;
+        if (t == 0) *dot_out = v;
     }
+}
+
+template <int N, bool DOT, typename T>
+__global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
+    int64_t E, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm, T lambda,
+    const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st)
+{
+    if constexpr (DOT) {
+        if (st->done) return;
+    }
+    ax_tile<N, DOT, T>(E, xcd_remap(blockIdx.x, gridDim.x), to_global(map), to_global(geo), to_global(Dm), lambda,
+                       to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));
 }
 
 template <int N>

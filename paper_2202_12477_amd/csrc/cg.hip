@@ -15,6 +15,7 @@
 #include <climits>
 #include <cmath>
 
+#include "cg_steps.h"
 #include "common.h"
 #include "reduce.h"
 
@@ -22,7 +23,6 @@ namespace hb {
 namespace {
 
 constexpr int kVecThreads = 256;
-constexpr int kFinThreads = 1024;
 
 
 template <typename V>
@@ -96,28 +96,10 @@ __global__ __launch_bounds__(kFinThreads) void init_finish_kernel(const double *
     }
 }
 
-// Start of iteration j = it + 1: alpha = rho_j / p.Ap, or stop on breakdown
-// (p.Ap <= 0 or not finite), or apply a stop decided by the previous beta.
 __global__ __launch_bounds__(kFinThreads) void alpha_kernel(const double *__restrict__ partial, int nblk, CgState *st,
                                                            const double *__restrict__ rho)
 {
-    if (st->done) return;
-    if (st->pending) {
-        if (threadIdx.x == 0) st->done = 1;
-        return;
-    }
-    __shared__ double red[kFinThreads / 64];
-    const double pAp = sum_partials(partial, nblk, red);
-    if (threadIdx.x != 0) return;
-    const int j = st->it + 1;
-    st->it = j;
-    st->pAp = pAp;
-    if (!(pAp > 0.0) || !isfinite(pAp)) {
-        st->done = 1;
-        st->status = HB_ERR_BREAKDOWN;
-    } else {
-        st->alpha = rho[j] / pAp;
-    }
+    alpha_step(partial, nblk, st, rho);
 }
 
 // r -= alpha Ap; partials of r.r.
@@ -139,30 +121,10 @@ __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, double
     if (threadIdx.x == 0) partial[blockIdx.x] = rr;
 }
 
-// rho_{j+1} = r.r, beta, history, convergence / iteration-cap test.
 __global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restrict__ partial, int nblk, CgState *st,
                                                           double *__restrict__ rho, double *__restrict__ hist)
 {
-    if (st->done) return;
-    __shared__ double red[kFinThreads / 64];
-    const double rho_new = sum_partials(partial, nblk, red);
-    if (threadIdx.x != 0) return;
-    const int j = st->it;
-    st->beta = rho_new / rho[j];
-    rho[j + 1] = rho_new;
-    hist[j + 1] = sqrt(rho_new);
-    st->iters = j + 1;
-    // this iteration's update still runs; the next alpha turns pending into done
-    if (!isfinite(rho_new)) {
-        st->pending = 1;
-        st->status = HB_ERR_BREAKDOWN;
-    } else if (rho_new == 0.0 || sqrt(rho_new) <= st->stop_res) {
-        st->pending = 1;
-        st->status = HB_OK;
-    } else if (j + 1 >= st->max_iter) {
-        st->pending = 1;
-        st->status = st->rtol >= 0.0 ? HB_ERR_NOT_CONVERGED : HB_OK;
-    }
+    beta_step(partial, nblk, st, rho, hist);
 }
 
 // x += alpha p; p = r + beta p; Ap = 0 (the next operator call assembles into it).

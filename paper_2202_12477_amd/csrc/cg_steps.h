@@ -1,0 +1,64 @@
+// The two single-block scalar steps of a CG iteration (Algorithm 1), shared
+// by the one-problem kernels and the batched kernels (one block per problem).
+#pragma once
+
+#include <cmath>
+
+#include "common.h"
+#include "reduce.h"
+
+namespace hb {
+
+constexpr int kFinThreads = 1024;
+
+// Start of iteration j = it + 1: alpha = rho_j / p.Ap, or stop on breakdown
+// (p.Ap <= 0 or not finite), or apply a stop decided by the previous beta.
+__device__ inline void alpha_step(const double *__restrict__ partial, int nblk, CgState *st,
+                                  const double *__restrict__ rho)
+{
+    __shared__ double red[kFinThreads / 64];
+    if (st->done) return;
+    if (st->pending) {
+        if (threadIdx.x == 0) st->done = 1;
+        return;
+    }
+    const double pAp = sum_partials(partial, nblk, red);
+    if (threadIdx.x != 0) return;
+    const int j = st->it + 1;
+    st->it = j;
+    st->pAp = pAp;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+        st->done = 1;
+        st->status = HB_ERR_BREAKDOWN;
+    } else {
+        st->alpha = rho[j] / pAp;
+    }
+}
+
+// rho_{j+1} = r.r, beta, history, convergence / iteration-cap test.
+__device__ inline void beta_step(const double *__restrict__ partial, int nblk, CgState *st, double *__restrict__ rho,
+                                 double *__restrict__ hist)
+{
+    __shared__ double red[kFinThreads / 64];
+    if (st->done) return;
+    const double rho_new = sum_partials(partial, nblk, red);
+    if (threadIdx.x != 0) return;
+    const int j = st->it;
+    st->beta = rho_new / rho[j];
+    rho[j + 1] = rho_new;
+    hist[j + 1] = sqrt(rho_new);
+    st->iters = j + 1;
+    // this iteration's update still runs; the next alpha turns pending into done
+    if (!isfinite(rho_new)) {
+        st->pending = 1;
+        st->status = HB_ERR_BREAKDOWN;
+    } else if (rho_new == 0.0 || sqrt(rho_new) <= st->stop_res) {
+        st->pending = 1;
+        st->status = HB_OK;
+    } else if (j + 1 >= st->max_iter) {
+        st->pending = 1;
+        st->status = st->rtol >= 0.0 ? HB_ERR_NOT_CONVERGED : HB_OK;
+    }
+}
+
+}  // namespace hb

@@ -52,6 +52,27 @@ struct CgState {
     int32_t status;    // hb_status of the solve
 };
 
+// One problem of a batched solve, as the batched kernels see it (device copy).
+struct BatchProb {
+    const int32_t *map;
+    const double *geo;
+    const float *geo32;
+    const double *D;
+    const float *D32;
+    double lambda;
+    double *x, *r, *p, *Ap;
+    float *Ap32;
+    double *rho, *hist, *part_ax, *part_vec;
+    CgState *st;
+    int64_t E, NG;
+    int32_t N, ax_tiles, vec_chunks, use32;  // use32: the operator of this problem is the FP32 one
+};
+
+// A unit of batched work: problem index and tile (operator) or chunk (vectors).
+struct WorkItem {
+    int32_t prob, idx;
+};
+
 // Per-mesh CG workspace (device), allocated on first use.
 struct CgWork {
     int64_t n = 0;         // N_G it was sized for
@@ -137,6 +158,17 @@ hb_status launch_residual_norm(int64_t n, const double *b, const double *t, doub
 hb_status launch_axpy(int64_t n, double *x, const double *d, hipStream_t s);
 // FP64 -> FP32 rounding of an array (geometry and D of HB_MESH_FP32 meshes).
 hb_status launch_round_f32(const double *in, float *out, int64_t n, hipStream_t s);
+
+// Batched kernels (batch.hip).  Vector chunks hold kBatchChunk entries.
+constexpr int kBatchChunk = 4096;
+int batch_ax_threads(int N);
+// D: the degree's derivative matrix (FP32 copy when fp32), shared by the class.
+hb_status launch_batch_ax(int N, const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
+                          hipStream_t s);
+hb_status launch_batch_alpha(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s);
+hb_status launch_batch_residual(const WorkItem *items, int nitems, const BatchProb *probs, hipStream_t s);
+hb_status launch_batch_beta(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s);
+hb_status launch_batch_update(const WorkItem *items, int nitems, const BatchProb *probs, hipStream_t s);
 
 // 8:1 streaming probe (stream.hip).
 hb_status launch_stream_probe(const double *in, double *out, int64_t n, hipStream_t s);
