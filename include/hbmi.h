@@ -213,6 +213,52 @@ hb_status hb_cg_solve(hb_mesh mesh, double lambda, const double *dev_b, double *
 hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lambdas, const double *const *dev_b,
                          double *const *dev_x, const hb_cg_opts *opts, hb_cg_result *results, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving engine: continuous batching of independent solve requests.       */
+/* A request is a box mesh (hb_mesh_desc), lambda, a forcing seed (the       */
+/* hb_rhs_uniform vector) and a tolerance.  hb_engine_step admits queued     */
+/* requests first-in first-out while a slot is free and the request's device */
+/* footprint fits in the budget (its mesh and forcing are built on the       */
+/* device at admission), advances every admitted request by a number of CG   */
+/* iterations in shared launches (as hb_batch_solve), and retires finished   */
+/* requests: the solution is copied to host memory (kept until polled) and   */
+/* the request's device memory is released.  An engine is not thread-safe.   */
+/* ------------------------------------------------------------------------ */
+typedef struct hb_engine_s *hb_engine;
+
+typedef struct {
+    size_t hbm_budget;      /* device bytes the admitted requests may hold in total */
+    int32_t max_slots;      /* requests solved at once */
+    int32_t prec;           /* HB_PREC_FP64 or HB_PREC_FP32_RR */
+    int32_t max_iter;       /* per-request CG iteration cap */
+    int32_t iters_per_step; /* iterations per hb_engine_step when its argument is <= 0 (<= 0: 25) */
+    double inner_rtol;      /* HB_PREC_FP32_RR replacement factor (<= 0: 1e-3) */
+} hb_engine_opts;
+
+typedef struct {
+    int32_t running;        /* admitted requests still iterating */
+    int32_t queued;         /* submitted, not yet admitted */
+    int32_t completed;      /* finished, not yet polled */
+    int32_t reserved;
+    size_t used_bytes;      /* footprint of the admitted requests */
+} hb_engine_info;
+
+/* Device bytes a request holds while admitted (pure host arithmetic). */
+hb_status hb_engine_footprint(const hb_mesh_desc *desc, int32_t prec, int32_t max_iter, size_t *bytes);
+hb_status hb_engine_create(const hb_engine_opts *opts, void *stream, hb_engine *out);
+/* Releases every device buffer (admitted requests are dropped).  NULL is accepted. */
+hb_status hb_engine_destroy(hb_engine engine);
+/* Queue a request; HB_ERR_BUDGET if its footprint exceeds the whole budget
+ * (it could never be admitted).  desc->flags is set by the engine. */
+hb_status hb_engine_submit(hb_engine engine, const hb_mesh_desc *desc, double lambda, uint64_t rhs_seed, double rtol,
+                           uint64_t *ticket);
+/* Admit, run `iters` iterations (<= 0: the engine default) of every admitted
+ * request, retire finished ones.  info may be NULL.  Synchronises the stream. */
+hb_status hb_engine_step(hb_engine engine, int32_t iters, hb_engine_info *info);
+/* *done = 1 and the results (host_x: N_G doubles, may be NULL) if the request
+ * has finished; the engine then forgets it.  *done = 0 otherwise. */
+hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, double *host_x, hb_cg_result *result);
+
 /* Empirical streaming probe of the Computational Tests section: every thread
  * reads 8 FP64 values and writes one (8:1 read:write), dev_out[i] =
  * sum_k dev_in[k*n + i], k = 0..7.  dev_in: 8n doubles, dev_out: n doubles.

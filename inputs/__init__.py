@@ -78,3 +78,24 @@ def batched_cases(count: int = 64, master_seed: int = 4) -> list:
     Ns = rng.choice([3, 5, 7, 9], size=count)
     return [BoxCase(f"batch{master_seed}_{i}_n{int(n)}_N{int(N)}", int(n), int(n), int(n), int(N), 0.05,
                     1000 * master_seed + i, 2000 * master_seed + i) for i, (n, N) in enumerate(zip(ns, Ns))]
+
+
+def serving_trace(count: int, rate: float = 200.0, master_seed: int = 5) -> list:
+    """Request stream: Poisson arrivals at `rate` per second; each request is a
+    near-cubic box whose element count E* is log-uniform in [8, 32768]
+    (nz = floor(E*^(1/3)), ny = floor(sqrt(E*/nz)), nx = round(E*/(ny nz))),
+    degree N ~ U{3,5,7,9,11}, jittered, its own seeds, lambda = 1.
+    Returns [(arrival_seconds, BoxCase)] for the first `count` arrivals."""
+    rng = np.random.default_rng(master_seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    estar = np.exp(rng.uniform(np.log(8.0), np.log(32768.0), size=count))
+    Ns = rng.choice([3, 5, 7, 9, 11], size=count)
+    out, t = [], 0.0
+    for i in range(count):
+        t += float(gaps[i])
+        e = float(estar[i])
+        nz = max(1, int(np.floor(e ** (1.0 / 3.0))))
+        ny = max(1, int(np.floor(np.sqrt(e / nz))))
+        nx = max(1, int(round(e / (ny * nz))))
+        out.append((t, BoxCase(f"req{i}", nx, ny, nz, int(Ns[i]), 0.05, 50000 + i, 60000 + i)))
+    return out

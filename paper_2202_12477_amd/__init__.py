@@ -35,8 +35,9 @@ PREC_FP32_RR = 2
 # Every entry point of include/hbmi.h, in declaration order.
 EXPORTS = (
     "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax",
-    "hb_ax_add", "hb_ax_f32", "hb_cg_solve", "hb_batch_solve", "hb_stream_probe", "hb_status_string",
-    "hb_last_error",
+    "hb_ax_add", "hb_ax_f32", "hb_cg_solve", "hb_batch_solve", "hb_engine_footprint", "hb_engine_create",
+    "hb_engine_destroy", "hb_engine_submit", "hb_engine_step", "hb_engine_poll", "hb_stream_probe",
+    "hb_status_string", "hb_last_error",
 )
 
 
@@ -55,6 +56,16 @@ class _MeshDesc(ctypes.Structure):
 class _MeshInfo(ctypes.Structure):
     _fields_ = [("n_elem", ctypes.c_int64), ("n_local", ctypes.c_int64), ("n_global", ctypes.c_int64),
                 ("N", ctypes.c_int32), ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+
+
+class _EngineOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("iters_per_step", ctypes.c_int32), ("inner_rtol", ctypes.c_double)]
+
+
+class _EngineInfo(ctypes.Structure):
+    _fields_ = [("running", ctypes.c_int32), ("queued", ctypes.c_int32), ("completed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("used_bytes", ctypes.c_size_t)]
 
 
 class _CgOpts(ctypes.Structure):
@@ -94,6 +105,12 @@ def lib() -> ctypes.CDLL:
         "hb_cg_solve": [vp, f64, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp, vp],
         "hb_batch_solve": [i32, vp, vp, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp],
         "hb_stream_probe": [vp, vp, i64, vp],
+        "hb_engine_footprint": [ctypes.POINTER(_MeshDesc), i32, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "hb_engine_create": [ctypes.POINTER(_EngineOpts), vp, ctypes.POINTER(vp)],
+        "hb_engine_destroy": [vp],
+        "hb_engine_submit": [vp, ctypes.POINTER(_MeshDesc), f64, u64, f64, ctypes.POINTER(ctypes.c_uint64)],
+        "hb_engine_step": [vp, i32, ctypes.POINTER(_EngineInfo)],
+        "hb_engine_poll": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), vp, ctypes.POINTER(_CgResult)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -273,6 +290,65 @@ def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool 
     if st in raise_on:
         _check(st, "hb_batch_solve")
     return st, [CgResult(r.iters, r.status, r.res0, r.res, r.bnorm, r.outer_iters, r.fp64_iters) for r in R]
+
+
+def request_footprint(nx: int, ny: int, nz: int, N: int, prec: int = PREC_FP64, max_iter: int = 100000) -> int:
+    """Device bytes a request of this size holds while the engine has it admitted."""
+    d = _MeshDesc(nx, ny, nz, N, 0.0, 0, MASS_GWJ, 0)
+    out = ctypes.c_size_t()
+    _check(lib().hb_engine_footprint(ctypes.byref(d), prec, max_iter, ctypes.byref(out)), "hb_engine_footprint")
+    return int(out.value)
+
+
+class Engine:
+    """Continuous-batching serving engine (hb_engine_*)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, prec: int = PREC_FP32_RR, max_iter: int = 100000,
+                 iters_per_step: int = 25, inner_rtol: float = 0.0, stream=None):
+        o = _EngineOpts(hbm_budget, max_slots, prec, max_iter, iters_per_step, inner_rtol)
+        h = ctypes.c_void_p()
+        self._stream = _stream(stream)
+        _check(lib().hb_engine_create(ctypes.byref(o), self._stream, ctypes.byref(h)), "hb_engine_create")
+        self._h = h
+        self._ng = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().hb_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, nx, ny, nz, N, *, jitter=0.05, seed=0, lam=1.0, rhs_seed=0, rtol=1e-8, mass=MASS_GWJ) -> int:
+        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, 0)
+        t = ctypes.c_uint64()
+        _check(lib().hb_engine_submit(self._h, ctypes.byref(d), lam, rhs_seed, rtol, ctypes.byref(t)),
+               "hb_engine_submit")
+        self._ng[t.value] = (nx * N + 1) * (ny * N + 1) * (nz * N + 1)
+        return int(t.value)
+
+    def step(self, iters: int = 0) -> dict:
+        info = _EngineInfo()
+        _check(lib().hb_engine_step(self._h, iters, ctypes.byref(info)), "hb_engine_step")
+        return dict(running=info.running, queued=info.queued, completed=info.completed, used_bytes=info.used_bytes)
+
+    def poll(self, ticket: int, want_x: bool = True):
+        """None while running, else (CgResult, x as numpy array or None)."""
+        import numpy as np
+
+        done = ctypes.c_int32()
+        r = _CgResult()
+        x = np.empty(self._ng[ticket]) if want_x else None
+        _check(lib().hb_engine_poll(self._h, ticket, ctypes.byref(done), x.ctypes.data if want_x else None,
+                                    ctypes.byref(r)), "hb_engine_poll")
+        if not done.value:
+            return None
+        del self._ng[ticket]
+        return CgResult(r.iters, r.status, r.res0, r.res, r.bnorm, r.outer_iters, r.fp64_iters), x
 
 
 def rhs_uniform(b, seed: int, stream=None):

@@ -20,6 +20,19 @@ void set_error(const std::string &msg);
 hb_status fail(hb_status st, const std::string &msg);
 hb_status hip_fail(hipError_t err, const char *what);
 
+// Device allocation that reports HB_ERR_OUT_OF_MEMORY and adds to *tally.
+template <typename T>
+inline hb_status dev_alloc(T **p, size_t count, size_t *tally)
+{
+    if (hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(HB_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(sizeof(T) * count) + " bytes failed");
+    }
+    *tally += sizeof(T) * count;
+    return HB_OK;
+}
+
 #define HB_HIP(call)                                      \
     do {                                                  \
         hipError_t err_ = (call);                         \

@@ -1,0 +1,580 @@
+// Batched CG runner and the continuous-batching serving engine.
+//
+// BatchRunner keeps a changing set of independent CG solves on the device and
+// advances all of them together (one operator launch per (degree, precision)
+// class, one launch per vector/scalar step; see batch.hip).  Problems join
+// between segments of iterations and leave as soon as they finish, so work
+// that arrives while others run is overlapped with them.
+//
+// The engine puts a request queue in front of it: a request (box mesh, degree,
+// lambda, forcing seed, tolerance) is admitted first-in first-out when a slot
+// is free and its device footprint fits the memory budget; admission builds
+// its mesh and forcing on the device; a finished request's solution is copied
+// to host memory and its device memory is released for the next admission.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+#include "solver.h"
+
+namespace hb {
+
+// ---------------------------------------------------------------------------
+// BatchRunner
+// ---------------------------------------------------------------------------
+class BatchRunner {
+  public:
+    BatchRunner(int capacity, hipStream_t s) : cap_(capacity), s_(s) {}
+    ~BatchRunner()
+    {
+        for (void *p : {(void *)probs_, (void *)states_, (void *)items_, (void *)plist_, (void *)norms_})
+            if (p) (void)hipFree(p);
+        for (void *p : {(void *)h_probs_, (void *)h_states_, (void *)h_items_, (void *)h_plist_, (void *)h_norms_,
+                        (void *)h_rho_})
+            if (p) (void)hipHostFree(p);
+    }
+
+    hb_status init()
+    {
+        slots_.resize(cap_);
+        if (hipMalloc(&probs_, sizeof(BatchProb) * cap_) != hipSuccess ||
+            hipMalloc(&states_, sizeof(CgState) * cap_) != hipSuccess ||
+            hipMalloc(&plist_, sizeof(int32_t) * cap_) != hipSuccess ||
+            hipMalloc(&norms_, sizeof(double) * cap_) != hipSuccess ||
+            hipHostMalloc(&h_probs_, sizeof(BatchProb) * cap_, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&h_states_, sizeof(CgState) * cap_, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&h_plist_, sizeof(int32_t) * cap_, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&h_norms_, sizeof(double) * cap_, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&h_rho_, sizeof(double) * cap_, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HB_ERR_OUT_OF_MEMORY, "batch runner: table allocation failed");
+        }
+        return HB_OK;
+    }
+
+    int free_slot() const
+    {
+        for (int i = 0; i < cap_; ++i)
+            if (!slots_[i].used) return i;
+        return -1;
+    }
+    int running() const
+    {
+        int n = 0;
+        for (const Slot &q : slots_) n += q.used && !q.finished;
+        return n;
+    }
+    bool finished(int i) const { return slots_[i].used && slots_[i].finished; }
+    const hb_cg_result &result(int i) const { return slots_[i].result; }
+    void release(int i)
+    {
+        slots_[i] = Slot{};
+        dirty_ = true;
+    }
+
+    // Start a solve in slot i (enqueued; its first state is read at the next step).
+    hb_status add(int i, hb_mesh_s *m, double lambda, const double *b, double *x, const hb_cg_opts &o)
+    {
+        const bool mixed = o.prec == HB_PREC_FP32_RR;
+        hb_status st;
+        if ((st = ensure_cg(m, o.max_iter, mixed))) return st;
+        Slot &q = slots_[i];
+        q = Slot{};
+        q.used = true;
+        q.starting = true;
+        q.mesh = m;
+        q.lambda = lambda;
+        q.b = b;
+        q.x = x;
+        q.opts = o;
+        q.mixed = mixed;
+        const double rtol = o.fixed_iters ? -1.0 : o.rtol;
+        if ((st = cg_start(m, lambda, b, x, states_ + i, o.x0_zero, o.max_iter, rtol, mixed, s_))) return st;
+        HB_HIP(hipMemcpyAsync(h_rho_ + i, m->cg.rho, sizeof(double), hipMemcpyDeviceToHost, s_));
+        CgWork &w = m->cg;
+        BatchProb &P = h_probs_[i];
+        P.map = m->map;
+        P.geo = m->geo;
+        P.geo32 = m->geo32;
+        P.D = m->D;
+        P.D32 = m->D32;
+        P.lambda = lambda;
+        P.x = x;
+        P.r = w.r;
+        P.p = w.p;
+        P.Ap = w.Ap;
+        P.Ap32 = w.Ap32;
+        P.rho = w.rho;
+        P.hist = w.hist;
+        P.part_ax = w.part_ax;
+        P.part_vec = w.part_vec;
+        P.st = states_ + i;
+        P.E = m->E;
+        P.NG = m->NG;
+        P.N = m->N;
+        P.ax_tiles = ax_blocks(m);
+        P.vec_chunks = static_cast<int32_t>((m->NG + kBatchChunk - 1) / kBatchChunk);
+        P.use32 = mixed ? 1 : 0;
+        dirty_ = true;
+        return HB_OK;
+    }
+
+    // Advance every running problem by `iters` iterations, then handle the
+    // problems the device stopped (finish, or replace the residual and resume).
+    hb_status step(int iters)
+    {
+        hb_status st;
+        if ((st = start_pending())) return st;
+        std::vector<int> run;
+        for (int i = 0; i < cap_; ++i)
+            if (slots_[i].used && !slots_[i].finished) run.push_back(i);
+        if (run.empty()) return HB_OK;
+        if (dirty_ && (st = build_lists(run))) return st;
+        for (int it = 0; it < iters; ++it) {
+            for (const Class &c : classes_)
+                if ((st = launch_batch_ax(c.N, c.D, c.fp32, items_ + c.off, c.count, probs_, s_))) return st;
+            if ((st = launch_batch_alpha(plist_, nrun_, probs_, s_)) ||
+                (st = launch_batch_residual(items_ + vec_off_, nvec_, probs_, s_)) ||
+                (st = launch_batch_beta(plist_, nrun_, probs_, s_)) ||
+                (st = launch_batch_update(items_ + vec_off_, nvec_, probs_, s_)))
+                return st;
+        }
+        return handle_stops(run);
+    }
+
+  private:
+    struct Slot {
+        bool used = false, starting = false, finished = false, mixed = false;
+        hb_mesh_s *mesh = nullptr;
+        double lambda = 0.0;
+        const double *b = nullptr;
+        double *x = nullptr;
+        hb_cg_opts opts{};
+        Replacer rp;
+        hb_cg_result result{};
+    };
+    struct Class {
+        int N;
+        bool fp32;
+        int off, count;
+        const void *D;  // the class's derivative matrix (any of its meshes)
+    };
+
+    // First state of newly added problems (one read-back for all of them).
+    hb_status start_pending()
+    {
+        bool any = false;
+        for (const Slot &q : slots_) any = any || (q.used && q.starting);
+        if (!any) return HB_OK;
+        HB_HIP(hipMemcpyAsync(h_states_, states_, sizeof(CgState) * cap_, hipMemcpyDeviceToHost, s_));
+        HB_HIP(hipStreamSynchronize(s_));
+        for (int i = 0; i < cap_; ++i) {
+            Slot &q = slots_[i];
+            if (!q.used || !q.starting) continue;
+            q.starting = false;
+            const CgState &hs = h_states_[i];
+            if (q.mixed) {
+                q.rp.start(&q.opts, std::sqrt(h_rho_[i]), std::sqrt(hs.bb), hs.done != 0,
+                           static_cast<hb_status>(hs.status));
+                if (q.rp.finished) {
+                    finish(i, hs.iters);
+                } else {
+                    hb_status st = launch_cg_resume(states_ + i, q.rp.threshold(), s_);
+                    if (st) return st;
+                }
+            } else if (hs.done) {
+                q.result = hb_cg_result{};
+                q.result.status = hs.status;
+                q.result.res0 = q.result.res = std::sqrt(h_rho_[i]);
+                q.result.bnorm = std::sqrt(hs.bb);
+                q.finished = true;
+            }
+        }
+        dirty_ = true;
+        return HB_OK;
+    }
+
+    hb_status grow_items(size_t n)
+    {
+        if (n <= items_cap_) return HB_OK;
+        size_t cap = std::max<size_t>(n, items_cap_ * 2);
+        if (items_) (void)hipFree(items_);
+        if (h_items_) (void)hipHostFree(h_items_);
+        items_ = nullptr;
+        h_items_ = nullptr;
+        items_cap_ = 0;
+        if (hipMalloc(&items_, sizeof(WorkItem) * cap) != hipSuccess ||
+            hipHostMalloc(&h_items_, sizeof(WorkItem) * cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HB_ERR_OUT_OF_MEMORY, "batch runner: work list allocation failed");
+        }
+        items_cap_ = cap;
+        return HB_OK;
+    }
+
+    // Work lists of the running problems: operator items grouped by (degree, precision).
+    hb_status build_lists(const std::vector<int> &run)
+    {
+        size_t need = 0;
+        for (int i : run) need += h_probs_[i].ax_tiles + h_probs_[i].vec_chunks;
+        hb_status st;
+        if ((st = grow_items(need))) return st;
+        // the previous lists may still be read by enqueued kernels: wait before rewriting the staging
+        HB_HIP(hipStreamSynchronize(s_));
+        HB_HIP(hipMemcpyAsync(probs_, h_probs_, sizeof(BatchProb) * cap_, hipMemcpyHostToDevice, s_));
+        classes_.clear();
+        int nit = 0;
+        for (int N = 1; N <= kMaxN; ++N)
+            for (int f = 0; f < 2; ++f) {
+                const int off = nit;
+                const void *D = nullptr;
+                for (int i : run) {
+                    const BatchProb &P = h_probs_[i];
+                    if (P.N != N || P.use32 != f) continue;
+                    D = f ? static_cast<const void *>(P.D32) : static_cast<const void *>(P.D);
+                    for (int t = 0; t < P.ax_tiles; ++t) h_items_[nit++] = WorkItem{i, t};
+                }
+                if (nit > off) classes_.push_back(Class{N, f != 0, off, nit - off, D});
+            }
+        vec_off_ = nit;
+        for (int i : run)
+            for (int c = 0; c < h_probs_[i].vec_chunks; ++c) h_items_[nit++] = WorkItem{i, c};
+        nvec_ = nit - vec_off_;
+        nrun_ = static_cast<int>(run.size());
+        for (int k = 0; k < nrun_; ++k) h_plist_[k] = run[k];
+        HB_HIP(hipMemcpyAsync(items_, h_items_, sizeof(WorkItem) * nit, hipMemcpyHostToDevice, s_));
+        HB_HIP(hipMemcpyAsync(plist_, h_plist_, sizeof(int32_t) * nrun_, hipMemcpyHostToDevice, s_));
+        dirty_ = false;
+        return HB_OK;
+    }
+
+    hb_status handle_stops(const std::vector<int> &run)
+    {
+        HB_HIP(hipMemcpyAsync(h_states_, states_, sizeof(CgState) * cap_, hipMemcpyDeviceToHost, s_));
+        HB_HIP(hipStreamSynchronize(s_));
+        std::vector<int> replaced, done64;
+        hb_status st;
+        for (int i : run) {
+            Slot &q = slots_[i];
+            const CgState &hs = h_states_[i];
+            const bool stopped = hs.done || hs.pending || hs.iters >= q.opts.max_iter;
+            if (!stopped) continue;
+            if (!q.mixed) {
+                done64.push_back(i);
+                HB_HIP(hipMemcpyAsync(h_norms_ + i, q.mesh->cg.rho + hs.iters, sizeof(double),
+                                      hipMemcpyDeviceToHost, s_));
+                continue;
+            }
+            bool enq = false;
+            if ((st = q.rp.replace(q.mesh, q.lambda, q.b, q.x, states_ + i, hs, norms_ + i, s_, &enq))) return st;
+            if (enq) {
+                replaced.push_back(i);
+                HB_HIP(hipMemcpyAsync(h_norms_ + i, norms_ + i, sizeof(double), hipMemcpyDeviceToHost, s_));
+            } else {
+                finish(i, hs.iters);
+            }
+        }
+        if (replaced.empty() && done64.empty()) return HB_OK;
+        HB_HIP(hipStreamSynchronize(s_));
+        for (int i : done64) {
+            Slot &q = slots_[i];
+            const CgState &hs = h_states_[i];
+            q.result = hb_cg_result{};
+            q.result.iters = hs.iters;
+            q.result.status = hs.status;
+            q.result.res0 = std::sqrt(h_rho_[i]);
+            q.result.res = std::sqrt(h_norms_[i]);
+            q.result.bnorm = std::sqrt(hs.bb);
+            q.finished = true;
+            dirty_ = true;
+        }
+        for (int i : replaced) {
+            Slot &q = slots_[i];
+            const bool was32 = q.rp.use32;
+            if ((st = q.rp.decide(q.mesh, states_ + i, h_states_[i].iters, h_norms_[i], nullptr, s_))) return st;
+            if (q.rp.finished) finish(i, h_states_[i].iters);
+            if (was32 != q.rp.use32) {
+                h_probs_[i].use32 = q.rp.use32 ? 1 : 0;
+                dirty_ = true;
+            }
+        }
+        return HB_OK;
+    }
+
+    void finish(int i, int iters)
+    {
+        Slot &q = slots_[i];
+        q.rp.fill(&q.result, iters);
+        q.finished = true;
+        dirty_ = true;
+    }
+
+    int cap_;
+    hipStream_t s_;
+    std::vector<Slot> slots_;
+    BatchProb *probs_ = nullptr, *h_probs_ = nullptr;
+    CgState *states_ = nullptr, *h_states_ = nullptr;
+    WorkItem *items_ = nullptr, *h_items_ = nullptr;
+    size_t items_cap_ = 0;
+    int32_t *plist_ = nullptr, *h_plist_ = nullptr;
+    double *norms_ = nullptr, *h_norms_ = nullptr, *h_rho_ = nullptr;
+    std::vector<Class> classes_;
+    int vec_off_ = 0, nvec_ = 0, nrun_ = 0;
+    bool dirty_ = true;
+};
+
+// ---------------------------------------------------------------------------
+// Serving engine
+// ---------------------------------------------------------------------------
+
+// Device bytes one request holds while it is admitted (mesh, FP32 copy,
+// CG workspace, b and x, histories).
+size_t request_footprint(const hb_mesh_desc &d, int prec, int max_iter)
+{
+    const double n1 = d.N + 1.0;
+    const double NL = (double)d.nx * d.ny * d.nz * n1 * n1 * n1;
+    const double NG = ((double)d.nx * d.N + 1) * ((double)d.ny * d.N + 1) * ((double)d.nz * d.N + 1);
+    const bool mixed = prec == HB_PREC_FP32_RR;
+    double bytes = NL * (4.0 + 8.0 * kGeo) + (mixed ? NL * 4.0 * kGeo : 0.0);  // map, geometry
+    bytes += NG * (8.0 * 3 + (mixed ? 4.0 : 0.0));                               // r, p, Ap (+ FP32 Ap)
+    bytes += NG * 16.0;                                                          // b, x
+    bytes += 16.0 * (max_iter + 1.0) + 8.0 * (NL / 16.0 + NG / 512.0) + 4096.0;  // histories, partials, small
+    return static_cast<size_t>(bytes);
+}
+
+}  // namespace hb
+
+struct hb_engine_s {
+    struct Request {
+        uint64_t ticket;
+        hb_mesh_desc desc;
+        double lambda;
+        uint64_t rhs_seed;
+        double rtol;
+        size_t footprint;
+    };
+    struct Active {
+        Request req;
+        hb_mesh mesh = nullptr;
+        double *b = nullptr, *x = nullptr;
+        int slot = -1;
+    };
+    struct Done {
+        hb_cg_result result;
+        std::vector<double> x;
+    };
+    hb_engine_opts opts;
+    hipStream_t s;
+    std::unique_ptr<hb::BatchRunner> runner;
+    std::deque<Request> queue;
+    std::vector<Active> active;
+    std::unordered_map<uint64_t, Done> done;
+    size_t used = 0;
+    uint64_t next_ticket = 1;
+
+    void release(Active &a)
+    {
+        if (a.b) (void)hipFree(a.b);
+        if (a.x) (void)hipFree(a.x);
+        if (a.mesh) hb_mesh_destroy(a.mesh);
+        used -= a.req.footprint;
+        a = Active{};
+    }
+};
+
+using namespace hb;
+
+extern "C" {
+
+hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lambdas, const double *const *dev_b,
+                         double *const *dev_x, const hb_cg_opts *opts, hb_cg_result *results, void *stream)
+{
+    if (nprob < 0 || (nprob > 0 && (!meshes || !lambdas || !dev_b || !dev_x || !results)) || !opts)
+        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: null argument");
+    if (opts->prec != HB_PREC_FP64 && opts->prec != HB_PREC_FP32_RR)
+        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: precision must be HB_PREC_FP64 or HB_PREC_FP32_RR");
+    const bool mixed = opts->prec == HB_PREC_FP32_RR;
+    const bool fixed = opts->fixed_iters != 0;
+    if (opts->max_iter < 0) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: max_iter must be >= 0");
+    if (mixed && fixed) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: mixed precision needs a tolerance");
+    if (!fixed && !(opts->rtol >= 0.0)) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: rtol must be >= 0");
+    for (int i = 0; i < nprob; ++i) {
+        if (!meshes[i] || !dev_b[i] || !dev_x[i] || dev_b[i] == dev_x[i])
+            return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": bad pointers");
+        if (!(lambdas[i] > 0.0) || !std::isfinite(lambdas[i]))
+            return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": lambda must be > 0");
+        if (mixed && !meshes[i]->geo32)
+            return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + " has no FP32 data");
+        for (int k = 0; k < i; ++k)
+            if (meshes[k] == meshes[i])
+                return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: a mesh appears twice (its workspace is per mesh)");
+    }
+    if (nprob == 0) return HB_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchRunner runner(nprob, s);
+    hb_status st;
+    if ((st = runner.init())) return st;
+    for (int i = 0; i < nprob; ++i)
+        if ((st = runner.add(i, meshes[i], lambdas[i], dev_b[i], dev_x[i], *opts))) return st;
+    const int chunk = fixed ? std::max(opts->max_iter, 1) : (opts->check_every > 0 ? opts->check_every : 25);
+    do {
+        if ((st = runner.step(chunk))) return st;
+    } while (runner.running() > 0);
+    hb_status worst = HB_OK;
+    for (int i = 0; i < nprob; ++i) {
+        results[i] = runner.result(i);
+        if (worst == HB_OK && results[i].status != HB_OK) worst = static_cast<hb_status>(results[i].status);
+    }
+    return worst;
+}
+
+hb_status hb_engine_footprint(const hb_mesh_desc *desc, int32_t prec, int32_t max_iter, size_t *bytes)
+{
+    if (!desc || !bytes || max_iter < 0) return fail(HB_ERR_INVALID_ARG, "hb_engine_footprint: bad arguments");
+    *bytes = request_footprint(*desc, prec, max_iter);
+    return HB_OK;
+}
+
+hb_status hb_engine_create(const hb_engine_opts *opts, void *stream, hb_engine *out)
+{
+    if (out) *out = nullptr;
+    if (!opts || !out) return fail(HB_ERR_INVALID_ARG, "hb_engine_create: null argument");
+    if (opts->max_slots < 1 || opts->hbm_budget == 0 || opts->max_iter < 1 ||
+        (opts->prec != HB_PREC_FP64 && opts->prec != HB_PREC_FP32_RR))
+        return fail(HB_ERR_INVALID_ARG, "hb_engine_create: bad options");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(HB_ERR_DEVICE, "no HIP device available");
+    }
+    hb_engine_s *e = new (std::nothrow) hb_engine_s();
+    if (!e) return fail(HB_ERR_OUT_OF_MEMORY, "hb_engine_create: host allocation failed");
+    e->opts = *opts;
+    e->s = static_cast<hipStream_t>(stream);
+    e->runner.reset(new (std::nothrow) BatchRunner(opts->max_slots, e->s));
+    e->active.resize(opts->max_slots);
+    hb_status st = e->runner ? e->runner->init() : fail(HB_ERR_OUT_OF_MEMORY, "hb_engine_create: host allocation");
+    if (st) {
+        delete e;
+        return st;
+    }
+    *out = e;
+    return HB_OK;
+}
+
+hb_status hb_engine_destroy(hb_engine e)
+{
+    if (!e) return HB_OK;
+    (void)hipStreamSynchronize(e->s);
+    for (hb_engine_s::Active &a : e->active)
+        if (a.mesh) e->release(a);
+    delete e;
+    return HB_OK;
+}
+
+hb_status hb_engine_submit(hb_engine e, const hb_mesh_desc *desc, double lambda, uint64_t rhs_seed, double rtol,
+                           uint64_t *ticket)
+{
+    if (!e || !desc || !ticket) return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: null argument");
+    if (desc->N < 1 || desc->N > kMaxN || desc->nx < 1 || desc->ny < 1 || desc->nz < 1 ||
+        !(desc->jitter >= 0.0 && desc->jitter < 0.5) || (desc->mass != HB_MASS_GWJ && desc->mass != HB_MASS_INVDEG))
+        return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: bad mesh descriptor");
+    if (!(lambda > 0.0) || !std::isfinite(lambda) || !(rtol > 0.0))
+        return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: lambda and rtol must be > 0");
+    const size_t fp = request_footprint(*desc, e->opts.prec, e->opts.max_iter);
+    if (fp > e->opts.hbm_budget)
+        return fail(HB_ERR_BUDGET, "hb_engine_submit: the request needs " + std::to_string(fp) +
+                                       " device bytes, more than the whole budget");
+    hb_engine_s::Request r{e->next_ticket++, *desc, lambda, rhs_seed, rtol, fp};
+    r.desc.flags = e->opts.prec == HB_PREC_FP32_RR ? HB_MESH_FP32 : 0;
+    e->queue.push_back(r);
+    *ticket = r.ticket;
+    return HB_OK;
+}
+
+hb_status hb_engine_step(hb_engine e, int32_t iters, hb_engine_info *info)
+{
+    if (!e) return fail(HB_ERR_INVALID_ARG, "hb_engine_step: null engine");
+    hb_status st;
+    // admission: first in, first out, while a slot is free and the footprint fits
+    while (!e->queue.empty()) {
+        const hb_engine_s::Request &r = e->queue.front();
+        const int slot = e->runner->free_slot();
+        if (slot < 0 || e->used + r.footprint > e->opts.hbm_budget) break;
+        hb_engine_s::Active a;
+        a.req = r;
+        a.slot = slot;
+        e->used += r.footprint;
+        if ((st = hb_mesh_create(&r.desc, e->s, &a.mesh))) {
+            e->release(a);
+            return st;
+        }
+        const int64_t NG = a.mesh->NG;
+        size_t tally = 0;
+        if ((st = dev_alloc(&a.b, NG, &tally)) || (st = dev_alloc(&a.x, NG, &tally)) ||
+            (st = launch_rhs(NG, r.rhs_seed, a.b, e->s))) {
+            e->release(a);
+            return st;
+        }
+        hb_cg_opts o{};
+        o.max_iter = e->opts.max_iter;
+        o.fixed_iters = 0;
+        o.rtol = r.rtol;
+        o.x0_zero = 1;
+        o.prec = e->opts.prec;
+        o.inner_rtol = e->opts.inner_rtol;
+        if ((st = e->runner->add(slot, a.mesh, r.lambda, a.b, a.x, o))) {
+            e->release(a);
+            return st;
+        }
+        e->active[slot] = a;
+        e->queue.pop_front();
+    }
+    const int k = iters > 0 ? iters : (e->opts.iters_per_step > 0 ? e->opts.iters_per_step : 25);
+    if ((st = e->runner->step(k))) return st;
+    // retire finished requests: solution to host memory, device memory released
+    for (int i = 0; i < e->opts.max_slots; ++i) {
+        hb_engine_s::Active &a = e->active[i];
+        if (!a.mesh || !e->runner->finished(i)) continue;
+        hb_engine_s::Done d;
+        d.result = e->runner->result(i);
+        d.x.resize(a.mesh->NG);
+        HB_HIP(hipMemcpyAsync(d.x.data(), a.x, sizeof(double) * a.mesh->NG, hipMemcpyDeviceToHost, e->s));
+        HB_HIP(hipStreamSynchronize(e->s));
+        e->done.emplace(a.req.ticket, std::move(d));
+        e->runner->release(i);
+        e->release(a);
+    }
+    if (info) {
+        info->running = e->runner->running();
+        info->queued = static_cast<int32_t>(e->queue.size());
+        info->completed = static_cast<int32_t>(e->done.size());
+        info->reserved = 0;
+        info->used_bytes = e->used;
+    }
+    return HB_OK;
+}
+
+hb_status hb_engine_poll(hb_engine e, uint64_t ticket, int32_t *done, double *host_x, hb_cg_result *result)
+{
+    if (!e || !done) return fail(HB_ERR_INVALID_ARG, "hb_engine_poll: null argument");
+    auto it = e->done.find(ticket);
+    if (it == e->done.end()) {
+        *done = 0;
+        return HB_OK;
+    }
+    *done = 1;
+    if (host_x) std::memcpy(host_x, it->second.x.data(), sizeof(double) * it->second.x.size());
+    if (result) *result = it->second.result;
+    e->done.erase(it);
+    return HB_OK;
+}
+
+}  // extern "C"

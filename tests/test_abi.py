@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 import paper_2202_12477_amd as hb
@@ -84,3 +86,42 @@ def test_no_device_is_reported(L):
     h = ctypes.c_void_p()
     assert L.hb_mesh_create(ctypes.byref(_desc()), None, ctypes.byref(h)) == hb.HB_ERR_DEVICE
     assert b"no HIP device" in L.hb_last_error()
+
+
+def test_engine_footprint_model(L):
+    """The admission footprint is the mesh (map + 7 FP64 factors, + 7 FP32 factors when mixed)
+    plus the CG vectors and b, x: about 60 (88 mixed) bytes per local node and 40 (44) per DOF."""
+    def fp(nx, ny, nz, N, prec):
+        return hb.request_footprint(nx, ny, nz, N, prec, max_iter=1000)
+    for (n, N) in [(4, 3), (10, 7), (16, 11)]:
+        NL, NG = n ** 3 * (N + 1) ** 3, (n * N + 1) ** 3
+        f64, f32 = fp(n, n, n, N, hb.PREC_FP64), fp(n, n, n, N, hb.PREC_FP32_RR)
+        assert 60 * NL + 40 * NG <= f64 <= 60 * NL + 40 * NG + 1.1 * NL + 50000
+        assert 88 * NL + 44 * NG <= f32 <= 88 * NL + 44 * NG + 1.1 * NL + 50000
+    assert fp(3, 3, 3, 5, 0) < fp(4, 3, 3, 5, 0) < fp(4, 3, 3, 6, 0)
+
+
+def test_engine_needs_device(L):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    o = hb._EngineOpts(1 << 30, 4, hb.PREC_FP64, 100, 25, 0.0)
+    h = ctypes.c_void_p()
+    assert L.hb_engine_create(ctypes.byref(o), None, ctypes.byref(h)) == hb.HB_ERR_DEVICE
+    assert L.hb_engine_destroy(None) == hb.HB_OK
+    bad = hb._EngineOpts(1 << 30, 0, hb.PREC_FP64, 100, 25, 0.0)
+    assert L.hb_engine_create(ctypes.byref(bad), None, ctypes.byref(h)) == hb.HB_ERR_INVALID_ARG
+
+
+def test_serving_trace_recipe():
+    import inputs
+
+    tr = inputs.serving_trace(2000)
+    t = np.array([a for a, _ in tr])
+    assert np.all(np.diff(t) > 0)
+    assert abs(len(t) / t[-1] - 200.0) < 20.0  # Poisson at 200 per second
+    E = np.array([c.E for _, c in tr])
+    assert E.min() >= 1 and E.max() <= 40000
+    assert abs(np.median(np.log(E)) - 0.5 * (np.log(8) + np.log(32768))) < 0.3  # log-uniform
+    assert set(c.N for _, c in tr) == {3, 5, 7, 9, 11}

@@ -1,0 +1,105 @@
+"""Continuous-batching engine (hb_engine_*) on the GPU.
+
+Requests arrive while others run, are admitted as slots and budget free up,
+share launches with the running ones, and are retired individually.  Each
+result must be the same alone and in the mix, within the tolerance it was
+solved to: ||A (x_mix - x_alone)|| <= 2 tol ||b||, and each one's true
+residual (FP64 oracle operator) meets the tolerance.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2202_12477_amd as hb  # noqa: E402
+
+TOL = 1e-8
+REQS = [inputs.BoxCase("r0", 2, 2, 2, 3, 0.05, 1, 101), inputs.BoxCase("r1", 3, 2, 2, 5, 0.05, 2, 102),
+        inputs.BoxCase("r2", 1, 1, 1, 11, 0.0, 3, 103), inputs.BoxCase("r3", 4, 4, 3, 3, 0.05, 4, 104),
+        inputs.BoxCase("r4", 2, 2, 2, 7, 0.05, 5, 105), inputs.BoxCase("r5", 3, 3, 3, 9, 0.05, 6, 106),
+        inputs.BoxCase("r6", 5, 1, 1, 3, 0.0, 7, 107), inputs.BoxCase("r7", 2, 3, 2, 5, 0.05, 8, 108)]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def alone(c, prec):
+    m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=prec != hb.PREC_FP64)
+    b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+    hb.rhs_uniform(b, c.rhs_seed)
+    x = torch.empty_like(b)
+    r = m.cg(c.lam, b, x, max_iter=100000, fixed_iters=False, rtol=TOL, prec=prec)
+    assert r.status == hb.HB_OK
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [hb.PREC_FP64, hb.PREC_FP32_RR])
+def test_engine_mix_equals_alone(prec):
+    say(f"[case] engine prec={prec}")
+    # a budget for about three of the larger requests at a time forces queueing
+    fps = [hb.request_footprint(c.nx, c.ny, c.nz, c.N, prec, 100000) for c in REQS]
+    budget = 3 * max(fps)
+    eng = hb.Engine(budget, max_slots=4, prec=prec, max_iter=100000, iters_per_step=20)
+    tickets = {}
+    results = {}
+    saw_queue = False
+    steps = 0
+    # two requests up front, then one more per step (arrivals while others run)
+    pending = list(REQS)
+    for c in pending[:2]:
+        tickets[eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, rhs_seed=c.rhs_seed,
+                           rtol=TOL)] = c
+    pending = pending[2:]
+    while len(results) < len(REQS):
+        if pending:
+            c = pending.pop(0)
+            tickets[eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, rhs_seed=c.rhs_seed,
+                               rtol=TOL)] = c
+        info = eng.step()
+        steps += 1
+        assert info["used_bytes"] <= budget
+        assert info["running"] <= 4
+        saw_queue = saw_queue or info["queued"] > 0
+        for t, c in tickets.items():
+            if t in results:
+                continue
+            out = eng.poll(t)
+            if out is not None:
+                results[t] = out
+        assert steps < 100000
+    assert saw_queue, "the budget never made a request wait"
+    for t, c in tickets.items():
+        r, x = results[t]
+        assert r.status == hb.HB_OK, (c.name, r)
+        ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+        bh = oracle.rhs(ref.NG, c.rhs_seed)
+        tr = np.linalg.norm(bh - ref.ax(x, c.lam)) / np.linalg.norm(bh)
+        xa = alone(c, prec)
+        d = np.linalg.norm(ref.ax(x - xa, c.lam)) / np.linalg.norm(bh)
+        say(f"{c.name}: iters {r.iters} true residual {tr:.2e}, |A(x_mix - x_alone)|/|b| {d:.2e}")
+        assert tr <= 1.2 * TOL
+        assert d <= 2.2 * TOL
+    eng.close()
+
+
+def test_engine_rejects_requests_larger_than_budget():
+    eng = hb.Engine(10 << 20, max_slots=2, prec=hb.PREC_FP64)
+    with pytest.raises(hb.HbError) as e:
+        eng.submit(16, 16, 16, 7)
+    assert e.value.status == hb.HB_ERR_BUDGET
+    t = eng.submit(2, 2, 2, 3, rhs_seed=5)
+    while eng.poll(t, want_x=False) is None:
+        eng.step()
+    eng.close()
