@@ -153,6 +153,10 @@ typedef struct {
     int32_t prec;        /* hb_prec */
     int32_t max_outer;   /* FP32_IR: cap on refinement steps (<=0: 60) */
     double inner_rtol;   /* FP32_IR: each inner solve stops at ||r_in|| <= inner_rtol ||r|| (<=0: 1e-3) */
+    int32_t graph_k;     /* hb_cg_solve: > 0 enqueues the iterations as replays of one captured HIP graph of
+                            graph_k iterations (cached per mesh for the same lambda, x and precision; a replay
+                            past the stop is a no-op on the device); 0: one launch per kernel. Ignored by
+                            hb_batch_solve. */
 } hb_cg_opts;
 
 typedef struct {

@@ -222,6 +222,8 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
     if (opts->max_iter < 0) return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: max_iter must be >= 0");
     if (!opts->fixed_iters && !(opts->rtol >= 0.0)) return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: rtol must be >= 0");
     if (dev_b == dev_x) return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: b and x must not alias");
+    if (opts->graph_k < 0 || opts->graph_k > 4096)
+        return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: graph_k must be in [0, 4096]");
     if (opts->prec != HB_PREC_FP64 && opts->prec != HB_PREC_FP32_IR && opts->prec != HB_PREC_FP32_RR)
         return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: unknown precision");
     const bool mixed = opts->prec != HB_PREC_FP64;
@@ -233,6 +235,7 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
     hb_status st = ensure_cg(m, opts->max_iter, mixed, opts->prec == HB_PREC_FP32_IR);
     if (st) return st;
     CgWork &w = m->cg;
+    w.graph_k = opts->graph_k;
     if (opts->prec == HB_PREC_FP32_RR) return solve_replace(m, lambda, dev_b, dev_x, opts, result, host_res_hist, s);
     if (!mixed) {
         if ((st = run_cg<double>(m, lambda, dev_b, dev_x, w.Ap, opts->x0_zero, opts->max_iter,

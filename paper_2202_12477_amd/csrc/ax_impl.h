@@ -7,9 +7,9 @@
 //   - the t-derivative and the t-part of D^T are register-only;
 //   - the r/s derivatives of layer c read one (N+1)^2 slice from LDS, and the
 //     r/s parts of D^T read one slice of f_r, f_s;
-//   - the rows/columns of D a thread needs live in registers (reused by every
-//     layer); D[c][*] is uniform across the block and comes through the
-//     scalar cache;
+//   - the rows of D a thread needs live in registers (reused by every layer),
+//     and so do its columns except where kColsInLds puts D^T in LDS;
+//     D[c][*] is uniform across the block and comes through the scalar cache;
 //   - each block holds EPB elements (EPB*(N+1)^2 <= 256 threads), so N=7 is
 //     one wave per element and low orders pack several elements per wave.
 // HBM streams: map (4 B/node) and the 7 geometric values once, coalesced per
@@ -50,6 +50,13 @@ struct AxShape {
     static constexpr int threads = (epb * np2 + 63) / 64 * 64;
 };
 
+// Where a thread keeps the columns of D for D^T: registers (reused by every
+// layer) or LDS (read per use; frees 2(N+1) registers).  LDS where that was
+// measured faster: FP64 at N = 11..14, where registers limit residency to one
+// wave per SIMD otherwise; FP32 at N = 9 and 14.
+template <int N, typename T>
+constexpr bool kColsInLds = sizeof(T) == 8 ? (N >= 11 && N <= 14) : (N == 9 || N == 14);
+
 // Materialise a value here: stops the compiler from sinking a layer's
 // arithmetic to the end of the kernel, which would keep every layer's LDS
 // operands live at once.
@@ -89,14 +96,22 @@ __device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __re
     const int64_t e = tile * epb + el;
     const bool active = lane_used && (e < E);
     const int64_t eo = e < E ? e : E - 1;  // inactive lanes read a valid element and discard it
-    // rows and columns a, b of D, loaded once and kept in registers
-    T Da[n1], Db[n1], DaT[n1], DbT[n1];
+    // rows a, b of D in registers, loaded once; columns a, b likewise, or D^T in LDS
+    constexpr bool cols_lds = kColsInLds<N, T>;
+    __shared__ T sDt[cols_lds ? np2 : 1];
+    T Da[n1], Db[n1], DaT[cols_lds ? 1 : n1], DbT[cols_lds ? 1 : n1];
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
         Da[m] = Dm[a * n1 + m];
         Db[m] = Dm[b * n1 + m];
-        DaT[m] = Dm[m * n1 + a];
-        DbT[m] = Dm[m * n1 + b];
+        if constexpr (!cols_lds) {
+            DaT[m] = Dm[m * n1 + a];
+            DbT[m] = Dm[m * n1 + b];
+        }
+    }
+    if constexpr (cols_lds) {
+        // sDt[i][m] = D[m][i]; the first layer's barriers order these stores before any read
+        for (int i = t; i < np2; i += S::threads) sDt[(i % n1) * n1 + i / n1] = Dm[i];
     }
 
     // gather through Z: the (a,b) column of the element
@@ -153,8 +168,14 @@ __device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __re
             ss[el][ab] = fs;
         }
         __syncthreads();
+        if constexpr (cols_lds) {
 #pragma unroll
-        for (int m = 0; m < n1; ++m) acc += DaT[m] * sr[el][b * n1 + m] + DbT[m] * ss[el][m * n1 + a];
+            for (int m = 0; m < n1; ++m)
+                acc += sDt[a * n1 + m] * sr[el][b * n1 + m] + sDt[b * n1 + m] * ss[el][m * n1 + a];
+        } else {
+#pragma unroll
+            for (int m = 0; m < n1; ++m) acc += DaT[m] * sr[el][b * n1 + m] + DbT[m] * ss[el][m * n1 + a];
+        }
         pin(acc);
         yv[c] = acc;
     }
@@ -190,7 +211,8 @@ __global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
     const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st)
 {
     if constexpr (DOT) {
-        if (st->done) return;
+        // stopped, or stopping at the next alpha step (which reads no partials)
+        if (st->done | st->pending) return;
     }
     ax_tile<N, DOT, T>(E, xcd_remap(blockIdx.x, gridDim.x), to_global(map), to_global(geo), to_global(Dm), lambda,
                        to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));

@@ -48,7 +48,9 @@ __global__ __launch_bounds__(AxShape<N>::threads) void batch_ax_kernel(const Wor
     const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const int32_t prob = uniform(it.prob), tile = uniform(it.idx);
     const BatchProb &P = probs[prob];
-    if (uniform(to_global(uniform(P.st))->done)) return;
+    // a stopped problem, or one whose stop the next alpha step will apply, needs no operator
+    const auto st = to_global(uniform(P.st));
+    if (uniform(st->done) | uniform(st->pending)) return;
     const int64_t E = uniform(P.E);
     const auto map = to_global(uniform(P.map));
     const auto x = to_global(uniform(P.p));

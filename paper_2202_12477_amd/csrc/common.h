@@ -104,6 +104,18 @@ struct CgWork {
     CgState *host_state = nullptr;  // pinned mirror for read-back
     double *host_norm = nullptr;    // pinned mirror of dnorm
     size_t bytes = 0;               // device bytes held (counted in the mesh's device_bytes)
+    // captured iteration graphs (hb_cg_opts.graph_k), keyed by their arguments
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        int elem = 0;  // bytes per operator output entry (8: FP64 operator, 4: FP32)
+        int k = 0;
+        double lambda = 0.0;
+        const void *x = nullptr, *Ap = nullptr;
+    };
+    Graph graphs[2];
+    int graph_next = 0;
+    int graph_k = 0;           // the current solve's graph length (0: plain launches)
+    hipStream_t cap = nullptr; // private stream the graphs are captured on
 };
 
 }  // namespace hb

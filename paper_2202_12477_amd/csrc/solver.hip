@@ -10,6 +10,14 @@
 
 namespace hb {
 
+static void drop_graphs(CgWork &w)
+{
+    for (CgWork::Graph &g : w.graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g = CgWork::Graph{};
+    }
+}
+
 void free_cg(hb_mesh_s *m)
 {
     CgWork &w = m->cg;
@@ -19,6 +27,8 @@ void free_cg(hb_mesh_s *m)
     if (w.state) (void)hipFree(w.state);
     if (w.host_state) (void)hipHostFree(w.host_state);
     if (w.host_norm) (void)hipHostFree(w.host_norm);
+    drop_graphs(w);
+    if (w.cap) (void)hipStreamDestroy(w.cap);
     m->device_bytes -= w.bytes;
     w = CgWork{};
 }
@@ -85,35 +95,93 @@ hb_status read_state(CgWork &w, hipStream_t s)
     return HB_OK;
 }
 
+// One CG iteration (Algorithm 1, loop body) with the operator whose output
+// type is TAp: Ap = A p with p.Ap fused, alpha, r -= alpha Ap with r.r, beta,
+// x += alpha p and p = r + beta p (which also clears Ap for the next operator).
+template <typename TAp>
+static hb_status enqueue_iteration(hb_mesh_s *m, double lambda, double *x, TAp *Ap, hipStream_t s)
+{
+    CgWork &w = m->cg;
+    const int64_t n = m->NG;
+    hb_status e;
+    if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, s))) return e;
+    if ((e = launch_cg_alpha(w, ax_blocks(m), w.state, s))) return e;
+    if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, s))) return e;
+    if ((e = launch_cg_beta(n, w, w.state, s))) return e;
+    return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.state, s);
+}
+
+// k iterations as one executable graph: the cached one with the same
+// arguments, else captured on the workspace's private stream (every step of
+// an iteration is a kernel launch, so the graph holds kernel nodes only).
+template <typename TAp>
+static hb_status iteration_graph(hb_mesh_s *m, double lambda, double *x, TAp *Ap, int k, hipGraphExec_t *out)
+{
+    CgWork &w = m->cg;
+    for (const CgWork::Graph &g : w.graphs) {
+        if (g.exec && g.elem == static_cast<int>(sizeof(TAp)) && g.k == k && g.lambda == lambda && g.x == x &&
+            g.Ap == Ap) {
+            *out = g.exec;
+            return HB_OK;
+        }
+    }
+    if (!w.cap) HB_HIP(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking));
+    CgWork::Graph &g = w.graphs[w.graph_next];
+    w.graph_next ^= 1;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = CgWork::Graph{};
+    HB_HIP(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
+    hb_status st = HB_OK;
+    for (int i = 0; i < k && st == HB_OK; ++i) st = enqueue_iteration<TAp>(m, lambda, x, Ap, w.cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(w.cap, &graph);
+    if (st != HB_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st != HB_OK ? st : hip_fail(e, "hipStreamEndCapture");
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        g.exec = nullptr;
+        return hip_fail(ei, "hipGraphInstantiate");
+    }
+    g.elem = static_cast<int>(sizeof(TAp));
+    g.k = k;
+    g.lambda = lambda;
+    g.x = x;
+    g.Ap = Ap;
+    *out = g.exec;
+    return HB_OK;
+}
+
 // Enqueue CG iterations with the operator whose output type is TAp until
 // the device state stops the solve or max_iter iterations are complete; the
 // state is left in w.host_state.  Fixed mode (every iteration runs) enqueues
 // everything at once; otherwise the state is read back every `check_every`
-// iterations.
+// iterations.  With w.graph_k > 0 the iterations are replays of a captured
+// graph of graph_k iterations; replays past the device's stop do nothing.
 template <typename TAp>
 hb_status cg_iterate(hb_mesh_s *m, double lambda, double *x, TAp *Ap, int max_iter, bool fixed, int check_every,
                      hipStream_t s)
 {
     CgWork &w = m->cg;
-    const int64_t n = m->NG;
-    const int axg = ax_blocks(m);
     hb_status st;
-    auto enqueue_iteration = [&]() -> hb_status {
-        hb_status e;
-        if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, s))) return e;
-        if ((e = launch_cg_alpha(w, axg, w.state, s))) return e;
-        if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, s))) return e;
-        if ((e = launch_cg_beta(n, w, w.state, s))) return e;
-        return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.state, s);
-    };
     if ((st = read_state(w, s))) return st;
     int done_iters = w.host_state->iters;
     auto stopped = [&]() { return w.host_state->done || w.host_state->pending; };
     const int chunk = fixed ? std::max(max_iter - done_iters, 1) : (check_every > 0 ? check_every : 25);
+    hipGraphExec_t graph = nullptr;
+    if (w.graph_k > 0 && done_iters < max_iter && !stopped() &&
+        (st = iteration_graph<TAp>(m, lambda, x, Ap, w.graph_k, &graph)))
+        return st;
     while (done_iters < max_iter && !stopped()) {
         const int k = std::min(chunk, max_iter - done_iters);
-        for (int i = 0; i < k; ++i)
-            if ((st = enqueue_iteration())) return st;
+        if (graph) {
+            for (int i = 0; i < (k + w.graph_k - 1) / w.graph_k; ++i) HB_HIP(hipGraphLaunch(graph, s));
+        } else {
+            for (int i = 0; i < k; ++i)
+                if ((st = enqueue_iteration<TAp>(m, lambda, x, Ap, s))) return st;
+        }
         if ((st = read_state(w, s))) return st;
         done_iters = w.host_state->iters;
     }
