@@ -4,9 +4,13 @@ Workload: 32^3 affine hexahedra at N=7 (11,390,625 assembled DOFs, 16.8M local
 nodes, 7 FP64 geometric factors per node), lambda = 1, seeded U[-1,1) forcing.
 One step = the paper's operator protocol (50 back-to-back operator calls) plus
 one 100-iteration CG solve (the benchmark's fixed iteration count), all inputs
-resident in HBM.  Prints one JSON line.
+resident in HBM.  After the timed steps (outside them): 64 uneven problems
+solved one by one in FP64 vs batched (FP64, and FP32 operator with FP64
+residual replacement), and the first arrivals of the serving trace through the
+continuous-batching engine vs one at a time in FP64, all to 1e-8 relative
+residual.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batch] [--serve-requests R]
 """
 from __future__ import annotations
 
@@ -80,12 +84,72 @@ def cpu_baseline(case, reps=8):
                       f"({m.NG} DOFs), one thread, {dt:.1f} s"}
 
 
+def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
+    """The 64 uneven problems: one-by-one FP64 CG vs the batched solver (FP64 and
+    FP32 operator with FP64 residual replacement), all to rtol; solves/s."""
+    cases = inputs.batched_cases()
+    meshes, bs = [], []
+    for c in cases:
+        m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=True)
+        b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+        hb.rhs_uniform(b, c.rhs_seed)
+        meshes.append(m)
+        bs.append(b)
+    xs = [torch.empty_like(b) for b in bs]
+    out = {"problems": len(cases), "rtol": rtol, "n_global_total": int(sum(m.NG for m in meshes))}
+
+    def seq():
+        iters = 0
+        for c, m, b, x in zip(cases, meshes, bs, xs):
+            r = m.cg(c.lam, b, x, max_iter=100000, fixed_iters=False, rtol=rtol, history=False)
+            assert r.status == hb.HB_OK, r
+            iters += r.iters
+        return iters
+
+    def batch(prec):
+        st, res = hb.batch_solve(meshes, [c.lam for c in cases], bs, xs, max_iter=100000, rtol=rtol, prec=prec)
+        assert st == hb.HB_OK, [r.status for r in res]
+        return sum(r.iters for r in res)
+
+    for name, fn in (("sequential_fp64", seq), ("batched_fp64", lambda: batch(hb.PREC_FP64)),
+                     ("batched_fp32rr", lambda: batch(hb.PREC_FP32_RR))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"solves_per_s": round(len(cases) / dt, 3), "wall_s": round(dt, 3), "cg_iterations": iters}
+        print(f"# batch {name}: {len(cases) / dt:.2f} solves/s", file=sys.stderr, flush=True)
+    for m in meshes:
+        m.close()
+    return out
+
+
+def served_vs_sequential(hb, torch, inputs, count, rtol=1e-8):
+    """The first `count` arrivals of the serving trace through the engine (FP32
+    operator with FP64 residual replacement, 64 GB budget) and one at a time
+    with FP64 CG; solves/s and latency percentiles."""
+    from paper_2202_12477_amd import serving
+
+    trace = inputs.serving_trace(count)
+    out = {"requests": count, "rtol": rtol, "offered_per_s": round(count / trace[-1][0], 1),
+           "trace_s": round(trace[-1][0], 3), "hbm_budget_gb": 64}
+    out["engine_fp32rr"] = serving.replay_engine(trace, prec=hb.PREC_FP32_RR, rtol=rtol, progress=16)
+    print(f"# serving engine: {out['engine_fp32rr']}", file=sys.stderr, flush=True)
+    out["sequential_fp64"] = serving.replay_sequential(trace, rtol=rtol, progress=16)
+    print(f"# serving sequential: {out['sequential_fp64']}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solves comparison")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="arrivals of the serving trace to replay (0 skips the serving comparison)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the operator and CG of this library run on a single device "
@@ -171,6 +235,12 @@ def main():
         "frac_of_stream": round(achieved / B, 4),
         "wall_s": round(wall, 3),
     }
+    m.close()
+    del b, y, yk, x
+    if not args.no_batch:
+        out["batch"] = batched_vs_sequential(hb, torch, inputs)
+    if args.serve_requests > 0:
+        out["serving"] = served_vs_sequential(hb, torch, inputs, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)

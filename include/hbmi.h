@@ -237,6 +237,9 @@ typedef struct {
     int32_t max_iter;       /* per-request CG iteration cap */
     int32_t iters_per_step; /* iterations per hb_engine_step when its argument is <= 0 (<= 0: 25) */
     double inner_rtol;      /* HB_PREC_FP32_RR replacement factor (<= 0: 1e-3) */
+    int32_t max_quota;      /* iteration quota per step: a request whose iteration costs at most 1/2^k of
+                               the costliest running request's advances 2^k times the step's iterations,
+                               capped at max_quota (<= 0: 64; 1: every request advances equally) */
 } hb_engine_opts;
 
 typedef struct {

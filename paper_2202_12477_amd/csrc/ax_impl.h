@@ -41,12 +41,16 @@ __device__ inline gptr<T> to_global(T *p)
     return (gptr<T>)p;
 }
 
+#ifndef HB_WAVE_BLOCK
+#define HB_WAVE_BLOCK 0
+#endif
 template <int N>
 struct AxShape {
     static constexpr int n1 = N + 1;
     static constexpr int np2 = n1 * n1;
     static constexpr int np3 = np2 * n1;
-    static constexpr int epb = (256 / np2) > 0 ? (256 / np2) : 1;
+    static constexpr int target = (HB_WAVE_BLOCK && (N <= 3 || N == 7)) ? 64 : 256;
+    static constexpr int epb = (target / np2) > 0 ? (target / np2) : 1;
     static constexpr int threads = (epb * np2 + 63) / 64 * 64;
 };
 
@@ -56,6 +60,13 @@ struct AxShape {
 // wave per SIMD otherwise; FP32 at N = 9 and 14.
 template <int N, typename T>
 constexpr bool kColsInLds = sizeof(T) == 8 ? (N >= 11 && N <= 14) : (N == 9 || N == 14);
+
+// Geometry layers in flight ahead of the one being computed.
+#ifndef HB_PF
+#define HB_PF 2
+#endif
+template <int N, typename T>
+constexpr int kPrefetch = HB_PF;
 
 // Materialise a value here: stops the compiler from sinking a layer's
 // arithmetic to the end of the kernel, which would keep every layer's LDS
@@ -124,13 +135,16 @@ __device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __re
     for (int c = 0; c < n1; ++c) q[c] = static_cast<T>(x[idx[c]]);
 
     // G is streamed once: non-temporal loads keep it from evicting x and y from
-    // the caches.  Layers c+1 and c+2 are in flight while layer c is computed.
+    // the caches.  Layers c+1 .. c+PF are in flight while layer c is computed
+    // (a ring of PF register sets; the loop is unrolled, so slots are static).
+    constexpr int PF = kPrefetch<N, T> < n1 ? kPrefetch<N, T> : n1;
     gptr<const T> ge = geo + eo * kGeo * np3 + ab;
-    T Gn[kGeo], Gnn[kGeo];
+    T Gq[PF][kGeo];
 #pragma unroll
-    for (int f = 0; f < kGeo; ++f) Gn[f] = __builtin_nontemporal_load(&ge[f * np3]);
+    for (int p = 0; p < PF; ++p) {
 #pragma unroll
-    for (int f = 0; f < kGeo; ++f) Gnn[f] = __builtin_nontemporal_load(&ge[f * np3 + np2]);  // n1 >= 2
+        for (int f = 0; f < kGeo; ++f) Gq[p][f] = __builtin_nontemporal_load(&ge[f * np3 + p * np2]);
+    }
     T ft[n1], yv[n1];
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
@@ -139,12 +153,10 @@ __device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __re
         __builtin_amdgcn_sched_barrier(0);
         T G[kGeo];
 #pragma unroll
-        for (int f = 0; f < kGeo; ++f) G[f] = Gn[f];
+        for (int f = 0; f < kGeo; ++f) G[f] = Gq[c % PF][f];
+        if (c + PF < n1) {
 #pragma unroll
-        for (int f = 0; f < kGeo; ++f) Gn[f] = Gnn[f];
-        if (c + 2 < n1) {
-#pragma unroll
-            for (int f = 0; f < kGeo; ++f) Gnn[f] = __builtin_nontemporal_load(&ge[f * np3 + (c + 2) * np2]);
+            for (int f = 0; f < kGeo; ++f) Gq[c % PF][f] = __builtin_nontemporal_load(&ge[f * np3 + (c + PF) * np2]);
         }
         // t-derivative from registers; D[c][*] is uniform (scalar loads)
         T qt = 0;

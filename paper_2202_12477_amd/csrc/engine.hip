@@ -126,9 +126,15 @@ class BatchRunner {
         return HB_OK;
     }
 
-    // Advance every running problem by `iters` iterations, then handle the
-    // problems the device stopped (finish, or replace the residual and resume).
-    hb_status step(int iters)
+    // Advance the running problems, then handle the ones the device stopped
+    // (finish, or replace the residual and resume).  Every problem advances
+    // `iters` iterations times its quota multiplier: 1 with max_quota = 1;
+    // otherwise a problem whose iteration costs at most 1/2^k of the costliest
+    // running one's gets 2^k (capped at max_quota), so small problems are not
+    // held to the large ones' pace.  Sub-iteration j launches only the problems
+    // whose quota exceeds j: the lists are sorted by multiplier, so those are a
+    // prefix of each list.
+    hb_status step(int iters, int max_quota = 1)
     {
         hb_status st;
         if ((st = start_pending())) return st;
@@ -136,14 +142,20 @@ class BatchRunner {
         for (int i = 0; i < cap_; ++i)
             if (slots_[i].used && !slots_[i].finished) run.push_back(i);
         if (run.empty()) return HB_OK;
-        if (dirty_ && (st = build_lists(run))) return st;
-        for (int it = 0; it < iters; ++it) {
-            for (const Class &c : classes_)
-                if ((st = launch_batch_ax(c.N, c.D, c.fp32, items_ + c.off, c.count, probs_, s_))) return st;
-            if ((st = launch_batch_alpha(plist_, nrun_, probs_, s_)) ||
-                (st = launch_batch_residual(items_ + vec_off_, nvec_, probs_, s_)) ||
-                (st = launch_batch_beta(plist_, nrun_, probs_, s_)) ||
-                (st = launch_batch_update(items_ + vec_off_, nvec_, probs_, s_)))
+        max_quota = std::max(max_quota, 1);
+        if ((dirty_ || max_quota != built_quota_) && (st = build_lists(run, max_quota))) return st;
+        const int sub_iters = iters * top_mult_;
+        for (int j = 0; j < sub_iters; ++j) {
+            const int need = j / iters + 1;  // multiplier a problem needs to run sub-iteration j
+            for (const Class &c : classes_) {
+                const int n = count_at(c.levels, need);
+                if (n > 0 && (st = launch_batch_ax(c.N, c.D, c.fp32, items_ + c.off, n, probs_, s_))) return st;
+            }
+            const int nrun = count_at(run_levels_, need), nvec = count_at(vec_levels_, need);
+            if ((st = launch_batch_alpha(plist_, nrun, probs_, s_)) ||
+                (st = launch_batch_residual(items_ + vec_off_, nvec, probs_, s_)) ||
+                (st = launch_batch_beta(plist_, nrun, probs_, s_)) ||
+                (st = launch_batch_update(items_ + vec_off_, nvec, probs_, s_)))
                 return st;
         }
         return handle_stops(run);
@@ -160,12 +172,26 @@ class BatchRunner {
         Replacer rp;
         hb_cg_result result{};
     };
+    // Cumulative list length after the problems whose multiplier is >= mult.
+    struct Level {
+        int mult, count;
+    };
     struct Class {
         int N;
         bool fp32;
-        int off, count;
-        const void *D;  // the class's derivative matrix (any of its meshes)
+        int off;
+        const void *D;              // the class's derivative matrix (any of its meshes)
+        std::vector<Level> levels;  // items of the class's problems, by multiplier (descending)
     };
+    static int count_at(const std::vector<Level> &levels, int need)
+    {
+        int n = 0;
+        for (const Level &l : levels) {
+            if (l.mult < need) break;
+            n = l.count;
+        }
+        return n;
+    }
 
     // First state of newly added problems (one read-back for all of them).
     hb_status start_pending()
@@ -219,8 +245,11 @@ class BatchRunner {
         return HB_OK;
     }
 
-    // Work lists of the running problems: operator items grouped by (degree, precision).
-    hb_status build_lists(const std::vector<int> &run)
+    // Work lists of the running problems: operator items grouped by (degree,
+    // precision), vector chunks and the problem list, each ordered by quota
+    // multiplier (descending).  A problem's cost per iteration is its bytes
+    // streamed: operator (60 N_L FP64, 32 N_L FP32) plus vectors (~88 N_G).
+    hb_status build_lists(std::vector<int> run, int max_quota)
     {
         size_t need = 0;
         for (int i : run) need += h_probs_[i].ax_tiles + h_probs_[i].vec_chunks;
@@ -229,28 +258,49 @@ class BatchRunner {
         // the previous lists may still be read by enqueued kernels: wait before rewriting the staging
         HB_HIP(hipStreamSynchronize(s_));
         HB_HIP(hipMemcpyAsync(probs_, h_probs_, sizeof(BatchProb) * cap_, hipMemcpyHostToDevice, s_));
+        auto cost = [&](int i) {
+            const BatchProb &P = h_probs_[i];
+            const double nl = static_cast<double>(P.E) * (P.N + 1) * (P.N + 1) * (P.N + 1);
+            return (P.use32 ? 32.0 : 60.0) * nl + 88.0 * static_cast<double>(P.NG);
+        };
+        double wmax = 0.0;
+        for (int i : run) wmax = std::max(wmax, cost(i));
+        mult_.assign(cap_, 1);
+        for (int i : run) {
+            int m = 1;
+            while (m * 2 <= max_quota && cost(i) * (m * 2) <= wmax) m *= 2;
+            mult_[i] = m;
+        }
+        std::stable_sort(run.begin(), run.end(), [&](int a, int b) { return mult_[a] > mult_[b]; });
+        top_mult_ = mult_[run.front()];
         classes_.clear();
         int nit = 0;
         for (int N = 1; N <= kMaxN; ++N)
             for (int f = 0; f < 2; ++f) {
-                const int off = nit;
-                const void *D = nullptr;
+                Class c{N, f != 0, nit, nullptr, {}};
                 for (int i : run) {
                     const BatchProb &P = h_probs_[i];
                     if (P.N != N || P.use32 != f) continue;
-                    D = f ? static_cast<const void *>(P.D32) : static_cast<const void *>(P.D);
+                    c.D = f ? static_cast<const void *>(P.D32) : static_cast<const void *>(P.D);
                     for (int t = 0; t < P.ax_tiles; ++t) h_items_[nit++] = WorkItem{i, t};
+                    c.levels.push_back(Level{mult_[i], nit - c.off});
                 }
-                if (nit > off) classes_.push_back(Class{N, f != 0, off, nit - off, D});
+                if (!c.levels.empty()) classes_.push_back(std::move(c));
             }
         vec_off_ = nit;
-        for (int i : run)
+        vec_levels_.clear();
+        run_levels_.clear();
+        for (size_t k = 0; k < run.size(); ++k) {
+            const int i = run[k];
             for (int c = 0; c < h_probs_[i].vec_chunks; ++c) h_items_[nit++] = WorkItem{i, c};
-        nvec_ = nit - vec_off_;
-        nrun_ = static_cast<int>(run.size());
-        for (int k = 0; k < nrun_; ++k) h_plist_[k] = run[k];
+            vec_levels_.push_back(Level{mult_[i], nit - vec_off_});
+            run_levels_.push_back(Level{mult_[i], static_cast<int>(k) + 1});
+            h_plist_[k] = i;
+        }
+        const int nrun = static_cast<int>(run.size());
         HB_HIP(hipMemcpyAsync(items_, h_items_, sizeof(WorkItem) * nit, hipMemcpyHostToDevice, s_));
-        HB_HIP(hipMemcpyAsync(plist_, h_plist_, sizeof(int32_t) * nrun_, hipMemcpyHostToDevice, s_));
+        HB_HIP(hipMemcpyAsync(plist_, h_plist_, sizeof(int32_t) * nrun, hipMemcpyHostToDevice, s_));
+        built_quota_ = max_quota;
         dirty_ = false;
         return HB_OK;
     }
@@ -326,7 +376,9 @@ class BatchRunner {
     int32_t *plist_ = nullptr, *h_plist_ = nullptr;
     double *norms_ = nullptr, *h_norms_ = nullptr, *h_rho_ = nullptr;
     std::vector<Class> classes_;
-    int vec_off_ = 0, nvec_ = 0, nrun_ = 0;
+    std::vector<Level> vec_levels_, run_levels_;
+    std::vector<int> mult_;
+    int vec_off_ = 0, top_mult_ = 1, built_quota_ = 0;
     bool dirty_ = true;
 };
 
@@ -538,7 +590,7 @@ hb_status hb_engine_step(hb_engine e, int32_t iters, hb_engine_info *info)
         e->queue.pop_front();
     }
     const int k = iters > 0 ? iters : (e->opts.iters_per_step > 0 ? e->opts.iters_per_step : 25);
-    if ((st = e->runner->step(k))) return st;
+    if ((st = e->runner->step(k, e->opts.max_quota > 0 ? e->opts.max_quota : 64))) return st;
     // retire finished requests: solution to host memory, device memory released
     for (int i = 0; i < e->opts.max_slots; ++i) {
         hb_engine_s::Active &a = e->active[i];

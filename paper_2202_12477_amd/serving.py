@@ -1,0 +1,98 @@
+"""Request loops over a timed arrival trace: the continuous-batching engine and
+the plain one-at-a-time FP64 solver, with per-request latency.
+
+A trace is a list of (arrival_seconds, request) where a request has the fields
+nx, ny, nz, N, jitter, mesh_seed, rhs_seed and lam (for example
+`inputs.serving_trace`).  Time starts when the loop starts; a request's
+latency is its completion time minus its arrival time, so it includes queueing.
+Both loops solve every request to the same relative residual and fail loudly on
+any request that does not reach it.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import HB_OK, PREC_FP64, Engine, Mesh, rhs_uniform
+
+
+def _summary(lat, wall, iters, extra=None):
+    lat = np.asarray(lat)
+    out = {"requests": int(lat.size), "wall_s": round(wall, 3), "solves_per_s": round(lat.size / wall, 3),
+           "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
+           "mean_s": round(float(lat.mean()), 4), "cg_iterations": int(iters)}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, iters_per_step=25,
+                  max_iter=200000, progress=None):
+    """Submit each request when its arrival time has passed, step the engine while
+    anything is queued or running, and poll for completions after every step."""
+    import torch
+
+    eng = Engine(hbm_budget, max_slots=max_slots, prec=prec, max_iter=max_iter, iters_per_step=iters_per_step)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nxt, lat, iters, steps, waiting = 0, [], 0, 0, {}
+        while len(lat) < len(trace):
+            now = time.perf_counter() - t0
+            while nxt < len(trace) and trace[nxt][0] <= now:
+                arrival, c = trace[nxt]
+                t = eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, rhs_seed=c.rhs_seed,
+                               lam=c.lam, rtol=rtol)
+                waiting[t] = arrival
+                nxt += 1
+            if not waiting:
+                time.sleep(max(0.0, trace[nxt][0] - (time.perf_counter() - t0)))
+                continue
+            eng.step()
+            steps += 1
+            for t in list(waiting):
+                got = eng.poll(t, want_x=False)
+                if got is None:
+                    continue
+                res = got[0]
+                if res.status != HB_OK:
+                    raise RuntimeError(f"request {t} ended with status {res.status}")
+                lat.append(time.perf_counter() - t0 - waiting.pop(t))
+                iters += res.iters
+                if progress and len(lat) % progress == 0:
+                    print(f"  engine: {len(lat)}/{len(trace)} done at {time.perf_counter() - t0:.1f} s", flush=True)
+        wall = time.perf_counter() - t0
+    finally:
+        eng.close()
+    return _summary(lat, wall, iters, {"engine_steps": steps})
+
+
+def replay_sequential(trace, *, rtol=1e-8, max_iter=200000, progress=None):
+    """One request at a time in arrival order, FP64 CG (hb_cg_solve), the solution
+    copied to the host like the engine's retirement does."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, iters = [], 0
+    for arrival, c in trace:
+        now = time.perf_counter() - t0
+        if now < arrival:
+            time.sleep(arrival - now)
+        m = Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+        try:
+            b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+            rhs_uniform(b, c.rhs_seed)
+            x = torch.empty_like(b)
+            res = m.cg(c.lam, b, x, max_iter=max_iter, fixed_iters=False, rtol=rtol, prec=PREC_FP64, history=False)
+            x.cpu()
+        finally:
+            m.close()
+        if res.status != HB_OK:
+            raise RuntimeError(f"sequential request ended with status {res.status}")
+        lat.append(time.perf_counter() - t0 - arrival)
+        iters += res.iters
+        if progress and len(lat) % progress == 0:
+            print(f"  sequential: {len(lat)}/{len(trace)} done at {time.perf_counter() - t0:.1f} s", flush=True)
+    return _summary(lat, time.perf_counter() - t0, iters)
