@@ -266,6 +266,34 @@ hb_status hb_engine_step(hb_engine engine, int32_t iters, hb_engine_info *info);
  * has finished; the engine then forgets it.  *done = 0 otherwise. */
 hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, double *host_x, hb_cg_result *result);
 
+/* ------------------------------------------------------------------------ */
+/* Operator tile schedules and their autotuner.                              */
+/* The operator (single, CG and batched launches) runs one of up to four     */
+/* compiled tile schedules per (degree, precision) class: bit 0 reads the    */
+/* columns of D for the divergence from LDS instead of registers; bit 1 uses */
+/* one-wave workgroups (available for N <= 7, where an element fits in a     */
+/* wave) instead of 256-thread workgroups.  The choice changes the reduction */
+/* grouping of p.Ap and the order of assembly atomics only (results agree to */
+/* rounding).  The table is process-wide, starts from measured defaults, and */
+/* must not be changed while solves are in flight.  `prec`: HB_PREC_FP64     */
+/* selects the FP64 operator's entry, either mixed precision the FP32 one.   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t schedule;   /* the schedule chosen (now in the table) */
+    int32_t candidates; /* schedules timed */
+    double us[4];       /* mean launch time per schedule in microseconds; < 0: not available at this degree */
+} hb_tune_result;
+
+/* Current schedule of a class. */
+hb_status hb_get_schedule(int32_t N, int32_t prec, int32_t *schedule);
+/* Pin a class's schedule (HB_ERR_INVALID_ARG if it is not available at N). */
+hb_status hb_set_schedule(int32_t N, int32_t prec, int32_t schedule);
+/* Time every available schedule of a class on a synthetic jittered box of
+ * about 2^22 local nodes (built and freed here: device allocation), `reps`
+ * back-to-back y += A x launches each (<= 0: 20; at most 10000), and put the
+ * fastest in the table.  out may be NULL.  Synchronises `stream`. */
+hb_status hb_autotune(int32_t N, int32_t prec, int32_t reps, hb_tune_result *out, void *stream);
+
 /* Empirical streaming probe of the Computational Tests section: every thread
  * reads 8 FP64 values and writes one (8:1 read:write), dev_out[i] =
  * sum_k dev_in[k*n + i], k = 0..7.  dev_in: 8n doubles, dev_out: n doubles.

@@ -37,7 +37,7 @@ EXPORTS = (
     "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax",
     "hb_ax_add", "hb_ax_f32", "hb_cg_solve", "hb_batch_solve", "hb_engine_footprint", "hb_engine_create",
     "hb_engine_destroy", "hb_engine_submit", "hb_engine_step", "hb_engine_poll", "hb_stream_probe",
-    "hb_status_string", "hb_last_error",
+    "hb_status_string", "hb_last_error", "hb_get_schedule", "hb_set_schedule", "hb_autotune",
 )
 
 
@@ -81,6 +81,10 @@ class _CgResult(ctypes.Structure):
                 ("fp64_iters", ctypes.c_int32)]
 
 
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("candidates", ctypes.c_int32), ("us", ctypes.c_double * 4)]
+
+
 _lib = None
 
 
@@ -112,6 +116,9 @@ def lib() -> ctypes.CDLL:
         "hb_engine_submit": [vp, ctypes.POINTER(_MeshDesc), f64, u64, f64, ctypes.POINTER(ctypes.c_uint64)],
         "hb_engine_step": [vp, i32, ctypes.POINTER(_EngineInfo)],
         "hb_engine_poll": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), vp, ctypes.POINTER(_CgResult)],
+        "hb_get_schedule": [i32, i32, ctypes.POINTER(ctypes.c_int32)],
+        "hb_set_schedule": [i32, i32, i32],
+        "hb_autotune": [i32, i32, i32, ctypes.POINTER(_TuneResult), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -360,6 +367,30 @@ def rhs_uniform(b, seed: int, stream=None):
 
     _check(lib().hb_rhs_uniform(b.numel(), seed, _ptr(b, torch.float64), _stream(stream)), "hb_rhs_uniform")
     return b
+
+
+SCHED_COLS_LDS = 1
+SCHED_WAVE = 2
+
+
+def get_schedule(N: int, prec: int = PREC_FP64) -> int:
+    """The operator tile schedule of a (degree, precision) class (hb_get_schedule)."""
+    v = ctypes.c_int32()
+    _check(lib().hb_get_schedule(N, prec, ctypes.byref(v)), "hb_get_schedule")
+    return v.value
+
+
+def set_schedule(N: int, prec: int, schedule: int):
+    """Pin a class's tile schedule (hb_set_schedule)."""
+    _check(lib().hb_set_schedule(N, prec, schedule), "hb_set_schedule")
+
+
+def autotune(N: int, prec: int = PREC_FP64, reps: int = 20, stream=None) -> dict:
+    """Time every tile schedule of a class on the device and keep the fastest (hb_autotune)."""
+    r = _TuneResult()
+    _check(lib().hb_autotune(N, prec, reps, ctypes.byref(r), _stream(stream)), "hb_autotune")
+    return {"N": N, "prec": prec, "schedule": r.schedule, "candidates": r.candidates,
+            "us": {v: round(r.us[v], 2) for v in range(4) if r.us[v] >= 0}}
 
 
 def stream_probe(inp, out, stream=None):

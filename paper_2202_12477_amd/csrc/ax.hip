@@ -1,4 +1,8 @@
-// Dispatch of the fused operator by polynomial degree (compile-time N).
+// Dispatch of the fused operator by polynomial degree (compile-time N) and
+// tile schedule (run-time table per degree and precision).
+#include <algorithm>
+#include <atomic>
+
 #include "common.h"
 
 namespace hb {
@@ -8,12 +12,60 @@ namespace hb {
                             hipStream_t);                                                                       \
     hb_status launch_ax32_##n(const hb_mesh_s *, double, const double *, float *, double *, CgState *,          \
                               hipStream_t);                                                                     \
-    int ax_grid_##n(int64_t);
+    hb_status launch_batch_ax_##n(const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t);   \
+    int ax_grid_##n(int64_t, int);
 HB_DECL_AX(1) HB_DECL_AX(2) HB_DECL_AX(3) HB_DECL_AX(4) HB_DECL_AX(5) HB_DECL_AX(6) HB_DECL_AX(7) HB_DECL_AX(8)
 HB_DECL_AX(9) HB_DECL_AX(10) HB_DECL_AX(11) HB_DECL_AX(12) HB_DECL_AX(13) HB_DECL_AX(14) HB_DECL_AX(15)
 #undef HB_DECL_AX
 
 #define HB_ALL_N(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+
+namespace {
+
+// Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups), from the
+// per-degree measurements at about 2^24 local nodes: D^T in LDS where the
+// registers otherwise allow only one wave per SIMD (FP64 N = 11..14) and
+// where it measured faster for FP32 (N = 9, 14).
+constexpr int kDefaultSched[2][kMaxN + 1] = {
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0},  // FP64
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0},  // FP32
+};
+
+std::atomic<int> g_sched[2][kMaxN + 1] = {};
+std::atomic<int> g_epoch{0};
+std::atomic<bool> g_init{false};
+
+void init_table()
+{
+    bool expect = false;
+    if (!g_init.load(std::memory_order_acquire) && g_init.compare_exchange_strong(expect, true)) {
+        for (int p = 0; p < 2; ++p)
+            for (int n = 0; n <= kMaxN; ++n) g_sched[p][n].store(kDefaultSched[p][n]);
+    }
+}
+
+}  // namespace
+
+int ax_schedule(int N, bool fp32)
+{
+    init_table();
+    if (N < 1 || N > kMaxN) return 0;
+    return g_sched[fp32 ? 1 : 0][N].load(std::memory_order_relaxed);
+}
+
+bool ax_schedule_legal(int N, int v)
+{
+    return N >= 1 && N <= kMaxN && v >= 0 && v < kNumSched && (!(v & kSchedWave) || (N + 1) * (N + 1) <= 64);
+}
+
+void set_ax_schedule(int N, bool fp32, int v)
+{
+    init_table();
+    g_sched[fp32 ? 1 : 0][N].store(v, std::memory_order_relaxed);
+    g_epoch.fetch_add(1);
+}
+
+int ax_schedule_epoch() { return g_epoch.load(); }
 
 hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
                     hipStream_t s)
@@ -40,15 +92,37 @@ hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float 
     }
 }
 
-int ax_blocks(const hb_mesh_s *m)
+hb_status launch_batch_ax(int N, const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
+                          hipStream_t s)
 {
-    switch (m->N) {
+    switch (N) {
 #define HB_CASE(n) \
-    case n: return ax_grid_##n(m->E);
+    case n: return launch_batch_ax_##n(D, fp32, items, nitems, probs, s);
+        HB_ALL_N(HB_CASE)
+#undef HB_CASE
+    default: return fail(HB_ERR_INVALID_ARG, "unsupported degree N");
+    }
+}
+
+int ax_grid_for(int N, int64_t E, int sched)
+{
+    switch (N) {
+#define HB_CASE(n) \
+    case n: return ax_grid_##n(E, sched);
         HB_ALL_N(HB_CASE)
 #undef HB_CASE
     default: return 0;
     }
+}
+
+int ax_blocks(const hb_mesh_s *m, bool fp32) { return ax_grid_for(m->N, m->E, ax_schedule(m->N, fp32)); }
+
+int ax_blocks_max(const hb_mesh_s *m)
+{
+    int g = 0;
+    for (int v = 0; v < kNumSched; ++v)
+        if (ax_schedule_legal(m->N, v)) g = std::max(g, ax_grid_for(m->N, m->E, v));
+    return g;
 }
 
 }  // namespace hb

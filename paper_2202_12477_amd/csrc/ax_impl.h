@@ -8,7 +8,7 @@
 //   - the r/s derivatives of layer c read one (N+1)^2 slice from LDS, and the
 //     r/s parts of D^T read one slice of f_r, f_s;
 //   - the rows of D a thread needs live in registers (reused by every layer),
-//     and so do its columns except where kColsInLds puts D^T in LDS;
+//     and so do its columns unless the schedule puts D^T in LDS;
 //     D[c][*] is uniform across the block and comes through the scalar cache;
 //   - each block holds EPB elements (EPB*(N+1)^2 <= 256 threads), so N=7 is
 //     one wave per element and low orders pack several elements per wave.
@@ -22,6 +22,8 @@
 // FP32 operator of the mixed-precision solver: FP32 geometry and D, x rounded
 // to FP32 on load, FP32 accumulation and assembly).  x is FP64 in both.
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 #include "reduce.h"
@@ -41,32 +43,28 @@ __device__ inline gptr<T> to_global(T *p)
     return (gptr<T>)p;
 }
 
-#ifndef HB_WAVE_BLOCK
-#define HB_WAVE_BLOCK 0
-#endif
+// Tile schedules of the operator, chosen per (degree, precision) class at run
+// time (a table filled with measured defaults and rewritten by the autotuner):
+//   kSchedColsLds - a thread reads the columns of D for D^T from LDS instead of
+//                   keeping them in registers (frees 2(N+1) registers);
+//   kSchedWave    - one-wave workgroups of floor(64/(N+1)^2) elements instead of
+//                   256-thread workgroups: no element spans two waves, so the
+//                   per-layer barriers are wave-local (legal for N <= 7).
 template <int N>
+constexpr bool kWaveLegal = (N + 1) * (N + 1) <= 64;
+
+template <int N, int V = 0>
 struct AxShape {
     static constexpr int n1 = N + 1;
     static constexpr int np2 = n1 * n1;
     static constexpr int np3 = np2 * n1;
-    static constexpr int target = (HB_WAVE_BLOCK && (N <= 3 || N == 7)) ? 64 : 256;
+    static constexpr int target = ((V & kSchedWave) && kWaveLegal<N>) ? 64 : 256;
     static constexpr int epb = (target / np2) > 0 ? (target / np2) : 1;
     static constexpr int threads = (epb * np2 + 63) / 64 * 64;
 };
 
-// Where a thread keeps the columns of D for D^T: registers (reused by every
-// layer) or LDS (read per use; frees 2(N+1) registers).  LDS where that was
-// measured faster: FP64 at N = 11..14, where registers limit residency to one
-// wave per SIMD otherwise; FP32 at N = 9 and 14.
-template <int N, typename T>
-constexpr bool kColsInLds = sizeof(T) == 8 ? (N >= 11 && N <= 14) : (N == 9 || N == 14);
-
 // Geometry layers in flight ahead of the one being computed.
-#ifndef HB_PF
-#define HB_PF 2
-#endif
-template <int N, typename T>
-constexpr int kPrefetch = HB_PF;
+constexpr int kPrefetch = 2;
 
 // Materialise a value here: stops the compiler from sinking a layer's
 // arithmetic to the end of the kernel, which would keep every layer's LDS
@@ -86,13 +84,15 @@ __device__ inline void atomic_add(gptr<T> p, T v)
 // One tile of EPB elements starting at element tile*EPB: y += A x on them and,
 // with DOT, this block's sum of x_e . y_e written to *dot_out (thread 0).
 // Every thread of the block must call it (it synchronises the block).
-template <int N, bool DOT, typename T>
-__device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
+// (Always inlined: the single-problem and the batched kernel both call it, and
+// an out-of-line call would spill the whole register set.)
+template <int N, bool DOT, typename T, int V>
+__device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
                                gptr<const T> __restrict__ geo, gptr<const T> __restrict__ Dm, T lambda,
                                gptr<const double> __restrict__ x, gptr<T> __restrict__ y,
                                gptr<double> __restrict__ dot_out)
 {
-    using S = AxShape<N>;
+    using S = AxShape<N, V>;
     constexpr int n1 = S::n1, np2 = S::np2, np3 = S::np3, epb = S::epb;
     __shared__ T sq[epb][np2];
     __shared__ T sr[epb][np2];
@@ -108,7 +108,7 @@ __device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __re
     const bool active = lane_used && (e < E);
     const int64_t eo = e < E ? e : E - 1;  // inactive lanes read a valid element and discard it
     // rows a, b of D in registers, loaded once; columns a, b likewise, or D^T in LDS
-    constexpr bool cols_lds = kColsInLds<N, T>;
+    constexpr bool cols_lds = (V & kSchedColsLds) != 0;
     __shared__ T sDt[cols_lds ? np2 : 1];
     T Da[n1], Db[n1], DaT[cols_lds ? 1 : n1], DbT[cols_lds ? 1 : n1];
 #pragma unroll
@@ -137,7 +137,7 @@ __device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __re
     // G is streamed once: non-temporal loads keep it from evicting x and y from
     // the caches.  Layers c+1 .. c+PF are in flight while layer c is computed
     // (a ring of PF register sets; the loop is unrolled, so slots are static).
-    constexpr int PF = kPrefetch<N, T> < n1 ? kPrefetch<N, T> : n1;
+    constexpr int PF = kPrefetch < n1 ? kPrefetch : n1;
     gptr<const T> ge = geo + eo * kGeo * np3 + ab;
     T Gq[PF][kGeo];
 #pragma unroll
@@ -217,8 +217,8 @@ __device__ inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __re
     }
 }
 
-template <int N, bool DOT, typename T>
-__global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
+template <int N, bool DOT, typename T, int V>
+__global__ __launch_bounds__((AxShape<N, V>::threads)) void ax_kernel(
     int64_t E, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm, T lambda,
     const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st)
 {
@@ -226,36 +226,131 @@ __global__ __launch_bounds__(AxShape<N>::threads) void ax_kernel(
         // stopped, or stopping at the next alpha step (which reads no partials)
         if (st->done | st->pending) return;
     }
-    ax_tile<N, DOT, T>(E, xcd_remap(blockIdx.x, gridDim.x), to_global(map), to_global(geo), to_global(Dm), lambda,
-                       to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));
+    ax_tile<N, DOT, T, V>(E, xcd_remap(blockIdx.x, gridDim.x), to_global(map), to_global(geo), to_global(Dm),
+                          lambda, to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));
+}
+
+// Values read from a work list or a problem table are the same for the whole
+// block; saying so lets the compiler keep them (and everything derived from
+// them, such as the uniform entries of D) in scalar registers.
+__device__ inline int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uniform(int64_t v)
+{
+    const uint64_t u = static_cast<uint64_t>(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+template <typename P>
+__device__ inline P *uniform(P *p)
+{
+    return reinterpret_cast<P *>(uniform(reinterpret_cast<int64_t>(p)));
+}
+__device__ inline double uniform(double v)
+{
+    return __builtin_bit_cast(double, uniform(__builtin_bit_cast(int64_t, v)));
+}
+
+// The batched operator: one block per (problem, tile) item of a class's work
+// list, with p.Ap fused.  D depends only on the degree, so all problems of a
+// class share it; as a read-only kernel argument its block-uniform entries come
+// through scalar loads.
+template <int N, typename T, int V>
+__global__ __launch_bounds__((AxShape<N, V>::threads)) void batch_ax_kernel(const WorkItem *__restrict__ items,
+                                                                         const BatchProb *__restrict__ probs,
+                                                                         const T *__restrict__ Dm)
+{
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const int32_t prob = uniform(it.prob), tile = uniform(it.idx);
+    const BatchProb &P = probs[prob];
+    // a stopped problem, or one whose stop the next alpha step will apply, needs no operator
+    const auto st = to_global(uniform(P.st));
+    if (uniform(st->done) | uniform(st->pending)) return;
+    const int64_t E = uniform(P.E);
+    const auto map = to_global(uniform(P.map));
+    const auto x = to_global(uniform(P.p));
+    const auto part = to_global(uniform(P.part_ax) + tile);
+    if constexpr (sizeof(T) == 4)
+        ax_tile<N, true, float, V>(E, tile, map, to_global(uniform(P.geo32)), to_global(Dm),
+                                   static_cast<float>(uniform(P.lambda)), x, to_global(uniform(P.Ap32)), part);
+    else
+        ax_tile<N, true, double, V>(E, tile, map, to_global(uniform(P.geo)), to_global(Dm), uniform(P.lambda), x,
+                                    to_global(uniform(P.Ap)), part);
+}
+
+template <int N, int V>
+int ax_grid(int64_t E)
+{
+    return static_cast<int>((E + AxShape<N, V>::epb - 1) / AxShape<N, V>::epb);
+}
+
+// Run-time schedule -> compile-time instantiation.  A schedule with one-wave
+// workgroups at a degree where an element does not fit in a wave maps to the
+// same schedule without them.
+template <int N, typename F>
+decltype(auto) with_schedule(int v, F &&f)
+{
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, kWaveLegal<N> ? 2 : 0>;
+    using I3 = std::integral_constant<int, kWaveLegal<N> ? 3 : 1>;
+    switch (v) {
+    case 1: return f(I1{});
+    case 2: return f(I2{});
+    case 3: return f(I3{});
+    default: return f(I0{});
+    }
 }
 
 template <int N>
-int ax_grid(int64_t E)
+int ax_grid_sched(int64_t E, int v)
 {
-    return static_cast<int>((E + AxShape<N>::epb - 1) / AxShape<N>::epb);
+    return with_schedule<N>(v, [&](auto VV) { return ax_grid<N, decltype(VV)::value>(E); });
 }
 
 template <int N, typename T>
 hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambda, const double *x, T *y,
                       double *partial, CgState *st, hipStream_t s)
 {
-    const int grid = ax_grid<N>(m->E);
-    if (grid == 0) return HB_OK;
-    const T lam = static_cast<T>(lambda);
-    if (st)
-        ax_kernel<N, true, T><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y, partial, st);
-    else
-        ax_kernel<N, false, T><<<grid, AxShape<N>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y, nullptr,
-                                                                    nullptr);
-    HB_HIP(hipGetLastError());
-    return HB_OK;
+    return with_schedule<N>(ax_schedule(N, sizeof(T) == 4), [&](auto VV) -> hb_status {
+        constexpr int V = decltype(VV)::value;
+        const int grid = ax_grid<N, V>(m->E);
+        if (grid == 0) return HB_OK;
+        const T lam = static_cast<T>(lambda);
+        if (st)
+            ax_kernel<N, true, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y,
+                                                                             partial, st);
+        else
+            ax_kernel<N, false, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y,
+                                                                              nullptr, nullptr);
+        HB_HIP(hipGetLastError());
+        return HB_OK;
+    });
+}
+
+template <int N>
+hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
+                            hipStream_t s)
+{
+    if (nitems == 0) return HB_OK;
+    return with_schedule<N>(ax_schedule(N, fp32), [&](auto VV) -> hb_status {
+        constexpr int V = decltype(VV)::value;
+        if (fp32)
+            batch_ax_kernel<N, float, V><<<nitems, AxShape<N, V>::threads, 0, s>>>(items, probs,
+                                                                                  static_cast<const float *>(D));
+        else
+            batch_ax_kernel<N, double, V><<<nitems, AxShape<N, V>::threads, 0, s>>>(items, probs,
+                                                                                   static_cast<const double *>(D));
+        HB_HIP(hipGetLastError());
+        return HB_OK;
+    });
 }
 
 }  // namespace hb
 
-// One degree's entry points (FP64 and FP32 operator, grid size), expanded in
-// the per-range translation units so the instantiations compile in parallel.
+// One degree's entry points (FP64 and FP32 operator, batched operator, grid
+// size per schedule), expanded in the per-range translation units so the
+// instantiations compile in parallel.
 #define HB_AX_INSTANCE(n)                                                                                      \
     namespace hb {                                                                                             \
     hb_status launch_ax_##n(const hb_mesh_s *m, double l, const double *x, double *y, double *p, CgState *st,  \
@@ -268,5 +363,10 @@ hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambd
     {                                                                                                          \
         return launch_ax_n<n, float>(m, m->geo32, m->D32, l, x, y, p, st, s);                                  \
     }                                                                                                          \
-    int ax_grid_##n(int64_t E) { return ax_grid<n>(E); }                                                       \
+    hb_status launch_batch_ax_##n(const void *D, bool fp32, const WorkItem *it, int ni, const BatchProb *pr,   \
+                                  hipStream_t s)                                                               \
+    {                                                                                                          \
+        return launch_batch_ax_n<n>(D, fp32, it, ni, pr, s);                                                   \
+    }                                                                                                          \
+    int ax_grid_##n(int64_t E, int v) { return ax_grid_sched<n>(E, v); }                                       \
     }

@@ -17,52 +17,6 @@ namespace {
 
 constexpr int kVecThreads = 256;
 
-// Values read from the work list and the problem table are the same for the
-// whole block; saying so lets the compiler keep them (and everything derived
-// from them, such as the uniform entries of D) in scalar registers.
-__device__ inline int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ inline int64_t uniform(int64_t v)
-{
-    const uint64_t u = static_cast<uint64_t>(v);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
-    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
-}
-template <typename T>
-__device__ inline T *uniform(T *p)
-{
-    return reinterpret_cast<T *>(uniform(reinterpret_cast<int64_t>(p)));
-}
-__device__ inline double uniform(double v)
-{
-    return __builtin_bit_cast(double, uniform(__builtin_bit_cast(int64_t, v)));
-}
-
-// D depends only on the degree, so all problems of a class share it; as a
-// read-only kernel argument its block-uniform entries come through scalar loads.
-template <int N, typename T>
-__global__ __launch_bounds__(AxShape<N>::threads) void batch_ax_kernel(const WorkItem *__restrict__ items,
-                                                                      const BatchProb *__restrict__ probs,
-                                                                      const T *__restrict__ Dm)
-{
-    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    const int32_t prob = uniform(it.prob), tile = uniform(it.idx);
-    const BatchProb &P = probs[prob];
-    // a stopped problem, or one whose stop the next alpha step will apply, needs no operator
-    const auto st = to_global(uniform(P.st));
-    if (uniform(st->done) | uniform(st->pending)) return;
-    const int64_t E = uniform(P.E);
-    const auto map = to_global(uniform(P.map));
-    const auto x = to_global(uniform(P.p));
-    const auto part = to_global(uniform(P.part_ax) + tile);
-    if constexpr (sizeof(T) == 4)
-        ax_tile<N, true, float>(E, tile, map, to_global(uniform(P.geo32)), to_global(Dm),
-                                static_cast<float>(uniform(P.lambda)), x, to_global(uniform(P.Ap32)), part);
-    else
-        ax_tile<N, true, double>(E, tile, map, to_global(uniform(P.geo)), to_global(Dm), uniform(P.lambda), x,
-                                 to_global(uniform(P.Ap)), part);
-}
-
 __global__ __launch_bounds__(kFinThreads) void batch_alpha_kernel(const int32_t *__restrict__ plist,
                                                                  const BatchProb *__restrict__ probs)
 {
@@ -142,45 +96,7 @@ __global__ __launch_bounds__(kVecThreads) void batch_update_kernel(const WorkIte
     }
 }
 
-template <int N>
-hb_status batch_ax_n(const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
-                     hipStream_t s)
-{
-    if (fp32)
-        batch_ax_kernel<N, float><<<nitems, AxShape<N>::threads, 0, s>>>(items, probs, static_cast<const float *>(D));
-    else
-        batch_ax_kernel<N, double><<<nitems, AxShape<N>::threads, 0, s>>>(items, probs, static_cast<const double *>(D));
-    HB_HIP(hipGetLastError());
-    return HB_OK;
-}
-
 }  // namespace
-
-int batch_ax_threads(int N)
-{
-    switch (N) {
-#define HB_CASE(n) \
-    case n: return AxShape<n>::threads;
-        HB_CASE(1) HB_CASE(2) HB_CASE(3) HB_CASE(4) HB_CASE(5) HB_CASE(6) HB_CASE(7) HB_CASE(8)
-        HB_CASE(9) HB_CASE(10) HB_CASE(11) HB_CASE(12) HB_CASE(13) HB_CASE(14) HB_CASE(15)
-#undef HB_CASE
-    default: return 0;
-    }
-}
-
-hb_status launch_batch_ax(int N, const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
-                          hipStream_t s)
-{
-    if (nitems == 0) return HB_OK;
-    switch (N) {
-#define HB_CASE(n) \
-    case n: return batch_ax_n<n>(D, fp32, items, nitems, probs, s);
-        HB_CASE(1) HB_CASE(2) HB_CASE(3) HB_CASE(4) HB_CASE(5) HB_CASE(6) HB_CASE(7) HB_CASE(8)
-        HB_CASE(9) HB_CASE(10) HB_CASE(11) HB_CASE(12) HB_CASE(13) HB_CASE(14) HB_CASE(15)
-#undef HB_CASE
-    default: return fail(HB_ERR_INVALID_ARG, "unsupported degree N");
-    }
-}
 
 hb_status launch_batch_alpha(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s)
 {

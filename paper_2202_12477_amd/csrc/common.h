@@ -13,6 +13,8 @@
 namespace hb {
 
 constexpr int kMaxN = 15;
+// Operator tile schedules (bit flags): D^T read from LDS; one-wave workgroups.
+constexpr int kSchedColsLds = 1, kSchedWave = 2, kNumSched = 4;
 constexpr int kGeo = 7;  // G_rr, G_rs, G_rt, G_ss, G_st, G_tt, c
 
 // Thread-local error message behind hb_last_error().
@@ -107,7 +109,8 @@ struct CgWork {
     // captured iteration graphs (hb_cg_opts.graph_k), keyed by their arguments
     struct Graph {
         hipGraphExec_t exec = nullptr;
-        int elem = 0;  // bytes per operator output entry (8: FP64 operator, 4: FP32)
+        int elem = 0;   // bytes per operator output entry (8: FP64 operator, 4: FP32)
+        int epoch = 0;  // schedule-table version the kernels were captured under
         int k = 0;
         double lambda = 0.0;
         const void *x = nullptr, *Ap = nullptr;
@@ -153,7 +156,16 @@ hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *
 // The FP32 operator (mesh built with HB_MESH_FP32): x FP64, y FP32.
 hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float *y, double *partial, CgState *st,
                       hipStream_t s);
-int ax_blocks(const hb_mesh_s *m);
+// Operator blocks (tiles) of a mesh under the current schedule of its degree
+// and the given precision; the largest over all schedules (sizes partials).
+int ax_blocks(const hb_mesh_s *m, bool fp32);
+int ax_blocks_max(const hb_mesh_s *m);
+int ax_grid_for(int N, int64_t E, int sched);
+// Schedule table (per degree and precision), shared by every solve path.
+int ax_schedule(int N, bool fp32);
+bool ax_schedule_legal(int N, int sched);
+void set_ax_schedule(int N, bool fp32, int sched);
+int ax_schedule_epoch();
 
 // Vector kernels of CG (cg.hip).  TAp is the type of the operator output Ap
 // (double for the FP64 operator, float for the FP32 one); every other vector
@@ -186,7 +198,6 @@ hb_status launch_round_f32(const double *in, float *out, int64_t n, hipStream_t 
 
 // Batched kernels (batch.hip).  Vector chunks hold kBatchChunk entries.
 constexpr int kBatchChunk = 4096;
-int batch_ax_threads(int N);
 // D: the degree's derivative matrix (FP32 copy when fp32), shared by the class.
 hb_status launch_batch_ax(int N, const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
                           hipStream_t s);

@@ -119,7 +119,7 @@ class BatchRunner {
         P.E = m->E;
         P.NG = m->NG;
         P.N = m->N;
-        P.ax_tiles = ax_blocks(m);
+        P.ax_tiles = ax_blocks(m, mixed);  // recomputed with the lists (schedule, precision)
         P.vec_chunks = static_cast<int32_t>((m->NG + kBatchChunk - 1) / kBatchChunk);
         P.use32 = mixed ? 1 : 0;
         dirty_ = true;
@@ -251,18 +251,25 @@ class BatchRunner {
     // streamed: operator (60 N_L FP64, 32 N_L FP32) plus vectors (~88 N_G).
     hb_status build_lists(std::vector<int> run, int max_quota)
     {
+        // enqueued kernels may still read the previous lists and copies the
+        // host staging: wait before rewriting either
+        HB_HIP(hipStreamSynchronize(s_));
+        // operator tiles under the current schedule of each problem's class
+        // (sets the list lengths, so before sizing the lists)
+        for (int i : run) {
+            BatchProb &P = h_probs_[i];
+            P.ax_tiles = ax_grid_for(P.N, P.E, ax_schedule(P.N, P.use32 != 0));
+        }
         size_t need = 0;
         for (int i : run) need += h_probs_[i].ax_tiles + h_probs_[i].vec_chunks;
         hb_status st;
         if ((st = grow_items(need))) return st;
-        // the previous lists may still be read by enqueued kernels: wait before rewriting the staging
-        HB_HIP(hipStreamSynchronize(s_));
-        HB_HIP(hipMemcpyAsync(probs_, h_probs_, sizeof(BatchProb) * cap_, hipMemcpyHostToDevice, s_));
         auto cost = [&](int i) {
             const BatchProb &P = h_probs_[i];
             const double nl = static_cast<double>(P.E) * (P.N + 1) * (P.N + 1) * (P.N + 1);
             return (P.use32 ? 32.0 : 60.0) * nl + 88.0 * static_cast<double>(P.NG);
         };
+        HB_HIP(hipMemcpyAsync(probs_, h_probs_, sizeof(BatchProb) * cap_, hipMemcpyHostToDevice, s_));
         double wmax = 0.0;
         for (int i : run) wmax = std::max(wmax, cost(i));
         mult_.assign(cap_, 1);

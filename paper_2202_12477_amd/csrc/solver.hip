@@ -39,7 +39,7 @@ void free_cg(hb_mesh_s *m)
 hb_status ensure_cg(hb_mesh_s *m, int max_iter, bool mixed, bool refine)
 {
     CgWork &w = m->cg;
-    const int need_ax = ax_blocks(m);
+    const int need_ax = ax_blocks_max(m);  // any schedule of either precision
     const int need_vec = static_cast<int>(std::max<int64_t>(2 * vec_blocks(m->NG), (m->NG + kBatchChunk - 1) / kBatchChunk));
     if (w.r && w.n == m->NG && w.hist_len >= max_iter + 1 && w.part_ax_len >= need_ax &&
         w.part_vec_len >= need_vec && (!mixed || w.Ap32) && (!refine || w.rout))
@@ -105,7 +105,7 @@ static hb_status enqueue_iteration(hb_mesh_s *m, double lambda, double *x, TAp *
     const int64_t n = m->NG;
     hb_status e;
     if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, s))) return e;
-    if ((e = launch_cg_alpha(w, ax_blocks(m), w.state, s))) return e;
+    if ((e = launch_cg_alpha(w, ax_blocks(m, sizeof(TAp) == 4), w.state, s))) return e;
     if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, s))) return e;
     if ((e = launch_cg_beta(n, w, w.state, s))) return e;
     return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.state, s);
@@ -120,7 +120,7 @@ static hb_status iteration_graph(hb_mesh_s *m, double lambda, double *x, TAp *Ap
     CgWork &w = m->cg;
     for (const CgWork::Graph &g : w.graphs) {
         if (g.exec && g.elem == static_cast<int>(sizeof(TAp)) && g.k == k && g.lambda == lambda && g.x == x &&
-            g.Ap == Ap) {
+            g.Ap == Ap && g.epoch == ax_schedule_epoch()) {
             *out = g.exec;
             return HB_OK;
         }
@@ -130,6 +130,7 @@ static hb_status iteration_graph(hb_mesh_s *m, double lambda, double *x, TAp *Ap
     w.graph_next ^= 1;
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g = CgWork::Graph{};
+    const int epoch = ax_schedule_epoch();
     HB_HIP(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
     hb_status st = HB_OK;
     for (int i = 0; i < k && st == HB_OK; ++i) st = enqueue_iteration<TAp>(m, lambda, x, Ap, w.cap);
@@ -146,6 +147,7 @@ static hb_status iteration_graph(hb_mesh_s *m, double lambda, double *x, TAp *Ap
         return hip_fail(ei, "hipGraphInstantiate");
     }
     g.elem = static_cast<int>(sizeof(TAp));
+    g.epoch = epoch;
     g.k = k;
     g.lambda = lambda;
     g.x = x;

@@ -1,0 +1,133 @@
+// Autotuner of the operator's tile schedules.
+//
+// For one (degree, precision) class it builds a synthetic jittered box of
+// about 2^22 local nodes, times every schedule that is legal at that degree
+// (y += A x launched back to back, HIP events on the caller's stream), and
+// writes the fastest into the process-wide schedule table that the operator,
+// CG and batched launches read.  Get/set let a caller inspect or pin entries.
+#include <cmath>
+#include <limits>
+
+#include "common.h"
+
+using namespace hb;
+
+namespace {
+
+hb_status check_class(int32_t N, int32_t prec, const char *who)
+{
+    if (N < 1 || N > kMaxN) return fail(HB_ERR_INVALID_ARG, std::string(who) + ": N must be in [1, 15]");
+    if (prec != HB_PREC_FP64 && prec != HB_PREC_FP32_IR && prec != HB_PREC_FP32_RR)
+        return fail(HB_ERR_INVALID_ARG, std::string(who) + ": unknown precision");
+    return HB_OK;
+}
+
+struct TuneScratch {
+    hb_mesh mesh = nullptr;
+    double *x = nullptr;
+    void *y = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~TuneScratch()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (x) (void)hipFree(x);
+        if (y) (void)hipFree(y);
+        if (mesh) (void)hb_mesh_destroy(mesh);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+hb_status hb_get_schedule(int32_t N, int32_t prec, int32_t *schedule)
+{
+    hb_status st;
+    if ((st = check_class(N, prec, "hb_get_schedule"))) return st;
+    if (!schedule) return fail(HB_ERR_INVALID_ARG, "hb_get_schedule: null argument");
+    *schedule = ax_schedule(N, prec != HB_PREC_FP64);
+    return HB_OK;
+}
+
+hb_status hb_set_schedule(int32_t N, int32_t prec, int32_t schedule)
+{
+    hb_status st;
+    if ((st = check_class(N, prec, "hb_set_schedule"))) return st;
+    if (!ax_schedule_legal(N, schedule))
+        return fail(HB_ERR_INVALID_ARG, "hb_set_schedule: schedule not available at this degree");
+    set_ax_schedule(N, prec != HB_PREC_FP64, schedule);
+    return HB_OK;
+}
+
+hb_status hb_autotune(int32_t N, int32_t prec, int32_t reps, hb_tune_result *out, void *stream)
+{
+    hb_status st;
+    if ((st = check_class(N, prec, "hb_autotune"))) return st;
+    if (reps > 10000) return fail(HB_ERR_INVALID_ARG, "hb_autotune: reps must be <= 10000");
+    if (reps <= 0) reps = 20;
+    const bool fp32 = prec != HB_PREC_FP64;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = std::max(1, static_cast<int>(std::lround(std::cbrt(4194304.0 / std::pow(N + 1.0, 3)))));
+    hb_mesh_desc d{};
+    d.nx = d.ny = d.nz = n;
+    d.N = N;
+    d.jitter = 0.05;
+    d.seed = 1;
+    d.mass = HB_MASS_GWJ;
+    d.flags = fp32 ? HB_MESH_FP32 : 0;
+    TuneScratch t;
+    if ((st = hb_mesh_create(&d, stream, &t.mesh))) return st;
+    const int64_t NG = t.mesh->NG;
+    size_t tally = 0;
+    if ((st = dev_alloc(&t.x, NG, &tally)) || (st = launch_rhs(NG, 7, t.x, s))) return st;
+    if (fp32) {
+        float *y = nullptr;
+        if ((st = dev_alloc(&y, NG, &tally))) return st;
+        t.y = y;
+        if ((st = launch_zero(y, NG, s))) return st;
+    } else {
+        double *y = nullptr;
+        if ((st = dev_alloc(&y, NG, &tally))) return st;
+        t.y = y;
+        if ((st = launch_zero(y, NG, s))) return st;
+    }
+    HB_HIP(hipEventCreate(&t.e0));
+    HB_HIP(hipEventCreate(&t.e1));
+    auto apply = [&]() -> hb_status {
+        return fp32 ? launch_ax32(t.mesh, 1.0, t.x, static_cast<float *>(t.y), nullptr, nullptr, s)
+                    : launch_ax(t.mesh, 1.0, t.x, static_cast<double *>(t.y), nullptr, nullptr, s);
+    };
+    const int prev = ax_schedule(N, fp32);
+    hb_tune_result res{};
+    res.schedule = prev;
+    for (int v = 0; v < 4; ++v) res.us[v] = -1.0;
+    double best_us = std::numeric_limits<double>::infinity();
+    for (int v = 0; v < kNumSched; ++v) {
+        if (!ax_schedule_legal(N, v)) continue;
+        set_ax_schedule(N, fp32, v);
+        hb_status e = HB_OK;
+        for (int w = 0; w < 2 && !e; ++w) e = apply();
+        hipError_t he = e ? hipSuccess : hipEventRecord(t.e0, s);
+        for (int r = 0; r < reps && !e && he == hipSuccess; ++r) e = apply();
+        if (!e && he == hipSuccess) he = hipEventRecord(t.e1, s);
+        if (!e && he == hipSuccess) he = hipEventSynchronize(t.e1);
+        float ms = 0.0f;
+        if (!e && he == hipSuccess) he = hipEventElapsedTime(&ms, t.e0, t.e1);
+        if (e || he != hipSuccess) {
+            set_ax_schedule(N, fp32, prev);
+            return e ? e : hip_fail(he, "hb_autotune: timing");
+        }
+        res.us[v] = 1e3 * ms / reps;
+        ++res.candidates;
+        if (res.us[v] < best_us) {
+            best_us = res.us[v];
+            res.schedule = v;
+        }
+    }
+    set_ax_schedule(N, fp32, res.schedule);
+    if (out) *out = res;
+    return HB_OK;
+}
+
+}  // extern "C"

@@ -125,3 +125,34 @@ def test_serving_trace_recipe():
     assert E.min() >= 1 and E.max() <= 40000
     assert abs(np.median(np.log(E)) - 0.5 * (np.log(8) + np.log(32768))) < 0.3  # log-uniform
     assert set(c.N for _, c in tr) == {3, 5, 7, 9, 11}
+
+
+def test_schedule_table_validation(L):
+    """The operator schedule table is host state: its validation needs no device."""
+    v = ctypes.c_int32(-1)
+    assert L.hb_get_schedule(0, 0, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_get_schedule(16, 0, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
+    # measured defaults: D^T from LDS for FP64 N = 11..14
+    for N in range(1, 16):
+        assert hb.get_schedule(N, hb.PREC_FP64) == (hb.SCHED_COLS_LDS if 11 <= N <= 14 else 0)
+    # one-wave workgroups exist only where an element fits in a wave (N <= 7)
+    assert L.hb_set_schedule(8, 0, hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(7, 0, 4) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(7, 0, -1) == hb.HB_ERR_INVALID_ARG
+    before = hb.get_schedule(7, hb.PREC_FP32_RR)
+    hb.set_schedule(7, hb.PREC_FP32_RR, hb.SCHED_WAVE | hb.SCHED_COLS_LDS)
+    assert hb.get_schedule(7, hb.PREC_FP32_IR) == 3  # both mixed precisions name the FP32 operator
+    assert hb.get_schedule(7, hb.PREC_FP64) == 0
+    hb.set_schedule(7, hb.PREC_FP32_RR, before)
+    assert L.hb_autotune(0, 0, 5, None, None) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_autotune(3, 0, 10001, None, None) == hb.HB_ERR_INVALID_ARG
+
+
+def test_autotune_needs_device(L):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    assert L.hb_autotune(3, 0, 5, None, None) == hb.HB_ERR_DEVICE

@@ -1,0 +1,154 @@
+"""Operator tile schedules and their autotuner (hb_get/set_schedule, hb_autotune).
+
+Every schedule computes the same operator; only the grouping of the fused
+p.Ap partial sums and the order of the assembly atomics differ.  So under
+every legal schedule at every degree the operator meets the same bars as the
+default one (FP64: 1e-12 against the oracle; FP32: the derived FP32 bar), CG
+and batched solves agree with the default schedule to rounding, and the
+autotuner only ever installs a legal schedule.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from cg_envelope import compare_history, history_bar
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2202_12477_amd as hb  # noqa: E402
+
+DEV = torch.device("cuda:0")
+PRECS = (hb.PREC_FP64, hb.PREC_FP32_RR)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def legal(N):
+    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1]
+
+
+@pytest.fixture(autouse=True)
+def restore_table():
+    saved = {(N, p): hb.get_schedule(N, p) for N in range(1, 16) for p in PRECS}
+    yield
+    for (N, p), v in saved.items():
+        hb.set_schedule(N, p, v)
+
+
+# ragged tails for every block shape: E is not a multiple of the elements per
+# 256-thread or one-wave workgroup
+CASES = [(5, 3, 1, 1), (3, 2, 2, 2), (3, 3, 2, 3), (3, 2, 2, 4), (2, 3, 2, 5), (3, 2, 1, 6), (3, 2, 2, 7),
+         (2, 2, 1, 8), (2, 1, 2, 9), (1, 2, 1, 10), (2, 1, 1, 11), (1, 1, 2, 12), (1, 2, 1, 13), (1, 1, 1, 14),
+         (2, 1, 1, 15)]
+
+
+@pytest.mark.parametrize("nx,ny,nz,N", CASES)
+def test_every_schedule_matches_oracle(nx, ny, nz, N):
+    say(f"[case] schedules N={N} box {nx}x{ny}x{nz}")
+    m = hb.Mesh(nx, ny, nz, N, jitter=0.05, seed=30 + N, fp32=True)
+    ref = oracle.Mesh(nx, ny, nz, N, jitter=0.05, seed=30 + N)
+    x = inputs.random_vector(m.NG, 60 + N)
+    yref = ref.ax(x, 1.1)
+    xd = torch.as_tensor(x, device=DEV)
+    for v in legal(N):
+        hb.set_schedule(N, hb.PREC_FP64, v)
+        hb.set_schedule(N, hb.PREC_FP32_RR, v)
+        y = torch.full((m.NG,), float("nan"), dtype=torch.float64, device=DEV)
+        m.ax(1.1, xd, y)
+        e64 = relerr(host(y), yref)
+        y32 = torch.full((m.NG,), float("nan"), dtype=torch.float32, device=DEV)
+        m.ax_f32(1.1, xd, y32)
+        e32 = relerr(host(y32), yref)
+        say(f"  schedule {v}: FP64 {e64:.2e} FP32 {e32:.2e}")
+        assert e64 <= 1e-12, (N, v)
+        assert 1e-9 < e32 <= 2e-5, (N, v)
+    m.close()
+
+
+@pytest.mark.parametrize("v", [1, 2, 3])
+def test_cg_history_under_schedule(v):
+    """Fused p.Ap with another partial grouping: the small configuration's
+    100-iteration history stays inside the oracle envelope."""
+    c = inputs.PLAIN_SMALL
+    say(f"[case] CG small config, schedule {v}")
+    hb.set_schedule(c.N, hb.PREC_FP64, v)
+    m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+    ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+    b = torch.empty(m.NG, dtype=torch.float64, device=DEV)
+    hb.rhs_uniform(b, c.rhs_seed)
+    x = torch.empty_like(b)
+    res = m.cg(c.lam, b, x, max_iter=c.iters, fixed_iters=True)
+    assert res.status == hb.HB_OK and res.iters == c.iters
+    href, bar = history_bar(ref, oracle.rhs(m.NG, c.rhs_seed), c.lam, c.iters)
+    assert compare_history(res.history, href, bar) <= 1.0
+    m.close()
+
+
+def test_batch_under_wave_schedules_matches_default():
+    cases = [inputs.BoxCase("s1", 3, 2, 2, 1, 0.05, 1, 21), inputs.BoxCase("s3", 4, 3, 2, 3, 0.05, 2, 22),
+             inputs.BoxCase("s5", 2, 2, 3, 5, 0.05, 3, 23), inputs.BoxCase("s7", 3, 2, 2, 7, 0.05, 4, 24),
+             inputs.BoxCase("s9", 2, 2, 2, 9, 0.05, 5, 25)]
+    say("[case] batch FP64 under one-wave schedules vs default")
+
+    def run():
+        ms, bs, xs = [], [], []
+        for c in cases:
+            m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+            b = torch.empty(m.NG, dtype=torch.float64, device=DEV)
+            hb.rhs_uniform(b, c.rhs_seed)
+            ms.append(m)
+            bs.append(b)
+            xs.append(torch.empty_like(b))
+        st, res = hb.batch_solve(ms, [c.lam for c in cases], bs, xs, max_iter=60, fixed_iters=True)
+        assert st == hb.HB_OK
+        out = [host(x) for x in xs]
+        for m in ms:
+            m.close()
+        return out, res
+
+    x0, r0 = run()
+    for c in cases:
+        hb.set_schedule(c.N, hb.PREC_FP64, 3 if (c.N + 1) ** 2 <= 64 else 1)
+    x1, r1 = run()
+    for c, a, b, ra, rb in zip(cases, x0, x1, r0, r1):
+        assert ra.iters == rb.iters == 60, c.name
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(a), c.name
+
+
+@pytest.mark.parametrize("N,prec", [(3, hb.PREC_FP64), (7, hb.PREC_FP64), (7, hb.PREC_FP32_RR), (12, hb.PREC_FP64)])
+def test_autotune_installs_a_legal_schedule(N, prec):
+    say(f"[case] autotune N={N} prec={prec}")
+    out = hb.autotune(N, prec, reps=10)
+    say(f"  {out}")
+    assert out["candidates"] == len(legal(N))
+    assert sorted(out["us"]) == legal(N) and all(t > 0 for t in out["us"].values())
+    assert out["schedule"] in legal(N)
+    assert out["us"][out["schedule"]] == min(out["us"].values())
+    assert hb.get_schedule(N, prec) == out["schedule"]
+    # the operator under the installed schedule still matches the oracle
+    m = hb.Mesh(2, 2, 1, N, jitter=0.05, seed=3, fp32=True)
+    ref = oracle.Mesh(2, 2, 1, N, jitter=0.05, seed=3)
+    x = inputs.random_vector(m.NG, 5)
+    y = torch.empty(m.NG, dtype=torch.float64, device=DEV)
+    m.ax(1.0, torch.as_tensor(x, device=DEV), y)
+    assert relerr(host(y), ref.ax(x, 1.0)) <= 1e-12
+    m.close()
