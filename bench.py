@@ -68,7 +68,7 @@ def stream_rate(hb, torch, n=1 << 25, reps=10):
     return 9 * 8 * n / statistics.median(times) / 1e9
 
 
-def cpu_baseline(case, reps=8):
+def cpu_baseline(case, reps=60):
     """The oracle (plain C, single thread) timed on a bounded sample of the same workload."""
     import oracle
 

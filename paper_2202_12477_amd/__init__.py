@@ -96,6 +96,10 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2202_12477_amd.build` "
                           "(or __graft_entry__.build()); there is no CPU fallback")
+    # torch (which supplies device memory and streams) brings its own HIP runtime; loading it first
+    # makes this library bind to that same runtime, so both see one device context
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     sig = {

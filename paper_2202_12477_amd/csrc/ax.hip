@@ -2,6 +2,7 @@
 // tile schedule (run-time table per degree and precision).
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 
 #include "common.h"
 
@@ -22,26 +23,26 @@ HB_DECL_AX(9) HB_DECL_AX(10) HB_DECL_AX(11) HB_DECL_AX(12) HB_DECL_AX(13) HB_DEC
 
 namespace {
 
-// Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups), from the
-// per-degree measurements at about 2^24 local nodes: D^T in LDS where the
-// registers otherwise allow only one wave per SIMD (FP64 N = 11..14) and
-// where it measured faster for FP32 (N = 9, 14).
+// Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups): the
+// autotuner's choices on this part at about 2^22 local nodes per degree, kept
+// where the winner beat the plain schedule by more than ~2% (one-wave
+// workgroups at low degree, D^T in LDS where registers are scarce).
 constexpr int kDefaultSched[2][kMaxN + 1] = {
-    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0},  // FP64
-    {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0},  // FP32
+    // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
+    {0, 3, 2, 3, 3, 3, 3, 0, 0, 0, 0, 1, 1, 1, 1, 0},  // FP64
+    {0, 2, 2, 2, 3, 2, 3, 2, 0, 1, 0, 0, 0, 0, 1, 0},  // FP32
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};
 std::atomic<int> g_epoch{0};
-std::atomic<bool> g_init{false};
+std::once_flag g_init;
 
 void init_table()
 {
-    bool expect = false;
-    if (!g_init.load(std::memory_order_acquire) && g_init.compare_exchange_strong(expect, true)) {
+    std::call_once(g_init, [] {
         for (int p = 0; p < 2; ++p)
             for (int n = 0; n <= kMaxN; ++n) g_sched[p][n].store(kDefaultSched[p][n]);
-    }
+    });
 }
 
 }  // namespace

@@ -134,16 +134,19 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(16, 0, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
-    # measured defaults: D^T from LDS for FP64 N = 11..14
+    # measured defaults: one-wave workgroups at low degree, D^T from LDS for FP64 N = 11..14
+    fp64 = [3, 2, 3, 3, 3, 3, 0, 0, 0, 0, 1, 1, 1, 1, 0]
+    fp32 = [2, 2, 2, 3, 2, 3, 2, 0, 1, 0, 0, 0, 0, 1, 0]
     for N in range(1, 16):
-        assert hb.get_schedule(N, hb.PREC_FP64) == (hb.SCHED_COLS_LDS if 11 <= N <= 14 else 0)
+        assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
+        assert hb.get_schedule(N, hb.PREC_FP32_RR) == fp32[N - 1]
     # one-wave workgroups exist only where an element fits in a wave (N <= 7)
     assert L.hb_set_schedule(8, 0, hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(7, 0, 4) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(7, 0, -1) == hb.HB_ERR_INVALID_ARG
     before = hb.get_schedule(7, hb.PREC_FP32_RR)
-    hb.set_schedule(7, hb.PREC_FP32_RR, hb.SCHED_WAVE | hb.SCHED_COLS_LDS)
-    assert hb.get_schedule(7, hb.PREC_FP32_IR) == 3  # both mixed precisions name the FP32 operator
+    hb.set_schedule(7, hb.PREC_FP32_RR, hb.SCHED_COLS_LDS)
+    assert hb.get_schedule(7, hb.PREC_FP32_IR) == 1  # both mixed precisions name the FP32 operator
     assert hb.get_schedule(7, hb.PREC_FP64) == 0
     hb.set_schedule(7, hb.PREC_FP32_RR, before)
     assert L.hb_autotune(0, 0, 5, None, None) == hb.HB_ERR_INVALID_ARG
