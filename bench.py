@@ -39,14 +39,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(schedule):
     """HBM bytes per operator launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken from a different kernel source."""
+    or None when it is missing or was taken from a different kernel source or
+    tile schedule."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash() or rec.get("schedule") != schedule:
         return None
     return rec.get("bytes_per_launch")
 
@@ -205,7 +206,8 @@ def main():
     kern_s = t_kern / (AX_CALLS * args.steps)
     ax_bytes = metrics.ax_bytes_fused(NG, NL)
     achieved = ax_bytes / kern_s / 1e9
-    traffic = measured_traffic()
+    schedule = hb.get_schedule(case.N, hb.PREC_FP64)
+    traffic = measured_traffic(schedule)
     out = {
         "metric": "Ax GDOF/s",
         "value": round(ax_gdofs, 3),
@@ -224,7 +226,7 @@ def main():
                    "E": E, "N": case.N, "n_global": NG, "n_local": NL},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": f"ax_kernel<{case.N},false>", "kernel_us": round(kern_s * 1e6, 2),
+                     "kernel": f"ax_kernel<{case.N},false,double,{schedule}>", "kernel_us": round(kern_s * 1e6, 2),
                      "algorithmic_bytes": int(ax_bytes)},
         "ax_gdofs_kernel_only": round(NG / kern_s / 1e9, 3),
         "ax_gflops": round(metrics.ax_flops(E, case.N) / kern_s / 1e9, 1),

@@ -182,7 +182,8 @@ typedef struct {
  * FP32_IR (mixed precision): x_0 = x0; repeat { r = b - A x_k with the FP64
  * operator; stop if ||r|| <= rtol ||b||; solve A_32 d = r by CG (FP32 operator,
  * FP64 vectors, dot products, residual updates) from d = 0 to
- * ||r_in|| <= inner_rtol ||r||; x_{k+1} = x_k + d }.  If a refinement step
+ * ||r_in|| <= eta_k ||r||, eta_k = min(1/2, max(inner_rtol, rtol ||b|| / (2 ||r||)))
+ * (no tighter than the remaining reduction needs); x_{k+1} = x_k + d }.  If a refinement step
  * reduces ||r|| by less than a factor 2 (the FP32 operator's error times the
  * condition number is too large), the solve continues with FP64 CG from x and
  * reports it in fp64_iters.
@@ -288,11 +289,14 @@ typedef struct {
 hb_status hb_get_schedule(int32_t N, int32_t prec, int32_t *schedule);
 /* Pin a class's schedule (HB_ERR_INVALID_ARG if it is not available at N). */
 hb_status hb_set_schedule(int32_t N, int32_t prec, int32_t schedule);
-/* Time every available schedule of a class on a synthetic jittered box of
- * about 2^22 local nodes (built and freed here: device allocation), `reps`
- * back-to-back y += A x launches each (<= 0: 20; at most 10000), and put the
- * fastest in the table.  out may be NULL.  Synchronises `stream`. */
-hb_status hb_autotune(int32_t N, int32_t prec, int32_t reps, hb_tune_result *out, void *stream);
+/* Time every available schedule of a class on a synthetic jittered cubic box
+ * of about `local_nodes` local nodes (<= 0: 2^22; at most 2^30; the best
+ * schedule depends on the problem size, so tune at the size that will run),
+ * built and freed here (device allocation), `reps` back-to-back y += A x
+ * launches each (<= 0: 20; at most 10000), and put the fastest in the table.
+ * out may be NULL.  Synchronises `stream`. */
+hb_status hb_autotune(int32_t N, int32_t prec, int64_t local_nodes, int32_t reps, hb_tune_result *out,
+                      void *stream);
 
 /* Empirical streaming probe of the Computational Tests section: every thread
  * reads 8 FP64 values and writes one (8:1 read:write), dev_out[i] =

@@ -122,7 +122,7 @@ def lib() -> ctypes.CDLL:
         "hb_engine_poll": [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), vp, ctypes.POINTER(_CgResult)],
         "hb_get_schedule": [i32, i32, ctypes.POINTER(ctypes.c_int32)],
         "hb_set_schedule": [i32, i32, i32],
-        "hb_autotune": [i32, i32, i32, ctypes.POINTER(_TuneResult), vp],
+        "hb_autotune": [i32, i32, i64, i32, ctypes.POINTER(_TuneResult), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -389,10 +389,11 @@ def set_schedule(N: int, prec: int, schedule: int):
     _check(lib().hb_set_schedule(N, prec, schedule), "hb_set_schedule")
 
 
-def autotune(N: int, prec: int = PREC_FP64, reps: int = 20, stream=None) -> dict:
-    """Time every tile schedule of a class on the device and keep the fastest (hb_autotune)."""
+def autotune(N: int, prec: int = PREC_FP64, local_nodes: int = 0, reps: int = 20, stream=None) -> dict:
+    """Time every tile schedule of a class on a box of about `local_nodes` local nodes (0: 2^22)
+    and keep the fastest (hb_autotune)."""
     r = _TuneResult()
-    _check(lib().hb_autotune(N, prec, reps, ctypes.byref(r), _stream(stream)), "hb_autotune")
+    _check(lib().hb_autotune(N, prec, local_nodes, reps, ctypes.byref(r), _stream(stream)), "hb_autotune")
     return {"N": N, "prec": prec, "schedule": r.schedule, "candidates": r.candidates,
             "us": {v: round(r.us[v], 2) for v in range(4) if r.us[v] >= 0}}
 

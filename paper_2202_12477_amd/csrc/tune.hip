@@ -1,10 +1,11 @@
 // Autotuner of the operator's tile schedules.
 //
-// For one (degree, precision) class it builds a synthetic jittered box of
-// about 2^22 local nodes, times every schedule that is legal at that degree
-// (y += A x launched back to back, HIP events on the caller's stream), and
-// writes the fastest into the process-wide schedule table that the operator,
-// CG and batched launches read.  Get/set let a caller inspect or pin entries.
+// For one (degree, precision) class it builds a synthetic jittered box of a
+// requested size (about 2^22 local nodes by default), times every schedule
+// that is legal at that degree (y += A x launched back to back, HIP events on
+// the caller's stream), and writes the fastest into the process-wide schedule
+// table that the operator, CG and batched launches read.  Get/set let a
+// caller inspect or pin entries.
 #include <cmath>
 #include <limits>
 
@@ -60,15 +61,20 @@ hb_status hb_set_schedule(int32_t N, int32_t prec, int32_t schedule)
     return HB_OK;
 }
 
-hb_status hb_autotune(int32_t N, int32_t prec, int32_t reps, hb_tune_result *out, void *stream)
+hb_status hb_autotune(int32_t N, int32_t prec, int64_t local_nodes, int32_t reps, hb_tune_result *out,
+                      void *stream)
 {
     hb_status st;
     if ((st = check_class(N, prec, "hb_autotune"))) return st;
     if (reps > 10000) return fail(HB_ERR_INVALID_ARG, "hb_autotune: reps must be <= 10000");
+    if (local_nodes > (int64_t(1) << 30))
+        return fail(HB_ERR_INVALID_ARG, "hb_autotune: local_nodes must be <= 2^30");
     if (reps <= 0) reps = 20;
+    if (local_nodes <= 0) local_nodes = int64_t(1) << 22;
     const bool fp32 = prec != HB_PREC_FP64;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int n = std::max(1, static_cast<int>(std::lround(std::cbrt(4194304.0 / std::pow(N + 1.0, 3)))));
+    const int n = std::max(1, static_cast<int>(std::lround(std::cbrt(static_cast<double>(local_nodes) /
+                                                                     std::pow(N + 1.0, 3)))));
     hb_mesh_desc d{};
     d.nx = d.ny = d.nz = n;
     d.N = N;

@@ -135,7 +135,7 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
     # measured defaults: one-wave workgroups at low degree, D^T from LDS for FP64 N = 11..14
-    fp64 = [3, 2, 3, 3, 3, 3, 0, 0, 0, 0, 1, 1, 1, 1, 0]
+    fp64 = [3, 0, 3, 3, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0]
     fp32 = [2, 2, 2, 3, 2, 3, 2, 0, 1, 0, 0, 0, 0, 1, 0]
     for N in range(1, 16):
         assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
@@ -149,8 +149,9 @@ def test_schedule_table_validation(L):
     assert hb.get_schedule(7, hb.PREC_FP32_IR) == 1  # both mixed precisions name the FP32 operator
     assert hb.get_schedule(7, hb.PREC_FP64) == 0
     hb.set_schedule(7, hb.PREC_FP32_RR, before)
-    assert L.hb_autotune(0, 0, 5, None, None) == hb.HB_ERR_INVALID_ARG
-    assert L.hb_autotune(3, 0, 10001, None, None) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_autotune(0, 0, 0, 5, None, None) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_autotune(3, 0, 0, 10001, None, None) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_autotune(3, 0, (1 << 30) + 1, 5, None, None) == hb.HB_ERR_INVALID_ARG
 
 
 def test_autotune_needs_device(L):
@@ -158,4 +159,4 @@ def test_autotune_needs_device(L):
 
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    assert L.hb_autotune(3, 0, 5, None, None) == hb.HB_ERR_DEVICE
+    assert L.hb_autotune(3, 0, 0, 5, None, None) == hb.HB_ERR_DEVICE

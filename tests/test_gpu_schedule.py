@@ -137,7 +137,7 @@ def test_batch_under_wave_schedules_matches_default():
 @pytest.mark.parametrize("N,prec", [(3, hb.PREC_FP64), (7, hb.PREC_FP64), (7, hb.PREC_FP32_RR), (12, hb.PREC_FP64)])
 def test_autotune_installs_a_legal_schedule(N, prec):
     say(f"[case] autotune N={N} prec={prec}")
-    out = hb.autotune(N, prec, reps=10)
+    out = hb.autotune(N, prec, local_nodes=1 << 20, reps=10)
     say(f"  {out}")
     assert out["candidates"] == len(legal(N))
     assert sorted(out["us"]) == legal(N) and all(t > 0 for t in out["us"].values())
