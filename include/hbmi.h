@@ -182,7 +182,7 @@ typedef struct {
  * FP32_IR (mixed precision): x_0 = x0; repeat { r = b - A x_k with the FP64
  * operator; stop if ||r|| <= rtol ||b||; solve A_32 d = r by CG (FP32 operator,
  * FP64 vectors, dot products, residual updates) from d = 0 to
- * ||r_in|| <= eta_k ||r||, eta_k = min(1/2, max(inner_rtol, rtol ||b|| / (2 ||r||)))
+ * ||r_in|| <= eta_k ||r||, eta_k = max(inner_rtol, min(1/2, rtol ||b|| / (2 ||r||)))
  * (no tighter than the remaining reduction needs); x_{k+1} = x_k + d }.  If a refinement step
  * reduces ||r|| by less than a factor 2 (the FP32 operator's error times the
  * condition number is too large), the solve continues with FP64 CG from x and

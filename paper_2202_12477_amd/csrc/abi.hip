@@ -314,8 +314,9 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
         if (outer >= max_outer || inner_total >= opts->max_iter) break;
         res_prev = res;
         // inner solve A_32 d = r (r = b - A x is in w.rout), to eta, or only as far as the
-        // remaining reduction needs (with a factor 2 to spare) when that is less
-        const double inner = std::min(0.5, std::max(eta, 0.5 * opts->rtol * bnorm / res));
+        // remaining reduction needs (with a factor 2 to spare, and never looser than 1/2)
+        // when that is less
+        const double inner = std::max(eta, std::min(0.5, 0.5 * opts->rtol * bnorm / res));
         if ((st = run_cg<float>(m, lambda, w.rout, w.d, w.Ap32, 1, opts->max_iter - inner_total, inner,
                                 opts->check_every, s)))
             return st;
