@@ -103,3 +103,19 @@ def test_engine_rejects_requests_larger_than_budget():
     while eng.poll(t, want_x=False) is None:
         eng.step()
     eng.close()
+
+
+def test_request_loops_replay_a_trace():
+    """The request loops behind the serving measurement: both solve every request
+    of a timed trace and report consistent latency summaries."""
+    from paper_2202_12477_amd import serving
+
+    say("[case] serving request loops on a 4-request trace")
+    trace = [(0.0, REQS[0]), (0.001, REQS[1]), (0.002, REQS[6]), (0.05, REQS[3])]
+    a = serving.replay_engine(trace, prec=hb.PREC_FP32_RR, hbm_budget=1 << 30, max_slots=2, iters_per_step=10)
+    b = serving.replay_sequential(trace)
+    say(f"engine {a}\nsequential {b}")
+    for r in (a, b):
+        assert r["requests"] == 4 and r["solves_per_s"] > 0 and r["cg_iterations"] > 0
+        assert 0 < r["p50_s"] <= r["p99_s"] <= r["wall_s"]
+    assert a["engine_steps"] >= 1
