@@ -166,7 +166,18 @@ hb_status hb_mesh_export(hb_mesh m, double *host_geo, int32_t *host_map, double 
 {
     if (!m) return fail(HB_ERR_INVALID_ARG, "hb_mesh_export: null mesh");
     const int n1 = m->N + 1;
-    if (host_geo) HB_HIP(hipMemcpy(host_geo, m->geo, sizeof(double) * kGeo * m->NL, hipMemcpyDeviceToHost));
+    if (host_geo) {
+        // the device keeps each element layer-major ([E][layer][factor][(N+1)^2]);
+        // the exported format is factor-major ([E][factor][(N+1)^3])
+        std::vector<double> dev(static_cast<size_t>(kGeo) * m->NL);
+        HB_HIP(hipMemcpy(dev.data(), m->geo, sizeof(double) * dev.size(), hipMemcpyDeviceToHost));
+        const int64_t np2 = (int64_t)n1 * n1, np3 = np2 * n1;
+        for (int64_t e = 0; e < m->E; ++e)
+            for (int64_t c = 0; c < n1; ++c)
+                for (int f = 0; f < kGeo; ++f)
+                    std::memcpy(host_geo + (e * kGeo + f) * np3 + c * np2, dev.data() + ((e * n1 + c) * kGeo + f) * np2,
+                                sizeof(double) * np2);
+    }
     if (host_map) HB_HIP(hipMemcpy(host_map, m->map, sizeof(int32_t) * m->NL, hipMemcpyDeviceToHost));
     if (host_D) std::memcpy(host_D, m->h_D, sizeof(double) * n1 * n1);
     if (host_xi) std::memcpy(host_xi, m->h_xi, sizeof(double) * n1);

@@ -13,7 +13,8 @@
 //   - each block holds EPB elements (EPB*(N+1)^2 <= 256 threads), so N=7 is
 //     one wave per element and low orders pack several elements per wave.
 // HBM streams: map (4 B/node) and the 7 geometric values once, coalesced per
-// layer (G non-temporal, two layers ahead); x through an indirect
+// layer (G non-temporal, two layers ahead; stored layer-major per element, so
+// an element's factors are one sequential 56(N+1)^3-byte read); x through an indirect
 // (cache-friendly) gather; y by device-scope atomic adds into a zeroed vector
 // (atomics on every node: mixing plain stores into lines that other elements
 // update atomically measured far slower).
@@ -138,12 +139,13 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
     // the caches.  Layers c+1 .. c+PF are in flight while layer c is computed
     // (a ring of PF register sets; the loop is unrolled, so slots are static).
     constexpr int PF = kPrefetch < n1 ? kPrefetch : n1;
+    // geometry layout [E][layer c][factor f][(N+1)^2 nodes of the layer]
     gptr<const T> ge = geo + eo * kGeo * np3 + ab;
     T Gq[PF][kGeo];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
 #pragma unroll
-        for (int f = 0; f < kGeo; ++f) Gq[p][f] = __builtin_nontemporal_load(&ge[f * np3 + p * np2]);
+        for (int f = 0; f < kGeo; ++f) Gq[p][f] = __builtin_nontemporal_load(&ge[(p * kGeo + f) * np2]);
     }
     T ft[n1], yv[n1];
 #pragma unroll
@@ -156,7 +158,8 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
         for (int f = 0; f < kGeo; ++f) G[f] = Gq[c % PF][f];
         if (c + PF < n1) {
 #pragma unroll
-            for (int f = 0; f < kGeo; ++f) Gq[c % PF][f] = __builtin_nontemporal_load(&ge[f * np3 + (c + PF) * np2]);
+            for (int f = 0; f < kGeo; ++f)
+                Gq[c % PF][f] = __builtin_nontemporal_load(&ge[((c + PF) * kGeo + f) * np2]);
         }
         // t-derivative from registers; D[c][*] is uniform (scalar loads)
         T qt = 0;

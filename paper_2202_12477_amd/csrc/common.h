@@ -128,7 +128,7 @@ struct hb_mesh_s {
     int N = 0;
     int64_t E = 0, NL = 0, NG = 0;
     int32_t *map = nullptr;   // [E][(N+1)^3] global index per local node (rows of Z)
-    double *geo = nullptr;    // [E][7][(N+1)^3]
+    double *geo = nullptr;    // [E][N+1 layers][7 factors][(N+1)^2]: each element layer-major
     double *D = nullptr;      // [(N+1)^2] row-major
     double *xi = nullptr, *w = nullptr;  // device copies of the GLL nodes and weights
     float *geo32 = nullptr;   // FP32 copy of geo (HB_MESH_FP32), rounded once

@@ -115,14 +115,16 @@ __global__ void geometry_kernel(int nx, int ny, int nz, int N, const double *__r
     const double gt[3] = {c02 * invJ, c12 * invJ, c22 * invJ};
     const double wJ = w[a] * w[b] * w[c] * J;
     auto dot3 = [](const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
-    double *g = geo + e * kGeo * np3 + n;
-    g[0 * np3] = wJ * dot3(gr, gr);
-    g[1 * np3] = wJ * dot3(gr, gs);
-    g[2 * np3] = wJ * dot3(gr, gt);
-    g[3 * np3] = wJ * dot3(gs, gs);
-    g[4 * np3] = wJ * dot3(gs, gt);
-    g[5 * np3] = wJ * dot3(gt, gt);
-    g[6 * np3] = mass_invdeg ? 0.0 : wJ;
+    // layer-major per element: [E][N+1 layers][7 factors][(N+1)^2 nodes of the layer]
+    const int64_t np2 = (int64_t)n1 * n1;
+    double *g = geo + (e * np3 + c * np2) * kGeo + (n - c * np2);
+    g[0 * np2] = wJ * dot3(gr, gr);
+    g[1 * np2] = wJ * dot3(gr, gs);
+    g[2 * np2] = wJ * dot3(gr, gt);
+    g[3 * np2] = wJ * dot3(gs, gs);
+    g[4 * np2] = wJ * dot3(gs, gt);
+    g[5 * np2] = wJ * dot3(gt, gt);
+    g[6 * np2] = mass_invdeg ? 0.0 : wJ;
 }
 
 __global__ void count_kernel(int64_t nl, const int32_t *__restrict__ map, int32_t *__restrict__ mult)
@@ -131,13 +133,13 @@ __global__ void count_kernel(int64_t nl, const int32_t *__restrict__ map, int32_
     if (t < nl) atomicAdd(&mult[map[t]], 1);
 }
 
-__global__ void invdeg_kernel(int64_t nl, int64_t np3, const int32_t *__restrict__ map,
+__global__ void invdeg_kernel(int64_t nl, int64_t np3, int64_t np2, const int32_t *__restrict__ map,
                               const int32_t *__restrict__ mult, double *__restrict__ geo)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= nl) return;
-    const int64_t e = t / np3, n = t - e * np3;
-    geo[(e * kGeo + 6) * np3 + n] = 1.0 / static_cast<double>(mult[map[t]]);
+    const int64_t e = t / np3, n = t - e * np3, c = n / np2;
+    geo[(e * np3 + c * np2) * kGeo + 6 * np2 + (n - c * np2)] = 1.0 / static_cast<double>(mult[map[t]]);
 }
 
 inline unsigned blocks_for(int64_t n, int threads) { return static_cast<unsigned>((n + threads - 1) / threads); }
@@ -189,7 +191,8 @@ hb_status build_geometry(hb_mesh_s *m, hipStream_t s)
             }
             if ((e = hipMemsetAsync(mult, 0, sizeof(int32_t) * m->NG, s)) != hipSuccess) { st = hip_fail(e, "memset"); break; }
             count_kernel<<<blocks_for(m->NL, 256), 256, 0, s>>>(m->NL, m->map, mult);
-            invdeg_kernel<<<blocks_for(m->NL, 256), 256, 0, s>>>(m->NL, np3, m->map, mult, m->geo);
+            invdeg_kernel<<<blocks_for(m->NL, 256), 256, 0, s>>>(m->NL, np3, (int64_t)(m->N + 1) * (m->N + 1),
+                                                                   m->map, mult, m->geo);
             if ((e = hipGetLastError()) != hipSuccess) { st = hip_fail(e, "invdeg_kernel"); break; }
         }
         if ((e = hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) {
