@@ -24,13 +24,13 @@ HB_DECL_AX(9) HB_DECL_AX(10) HB_DECL_AX(11) HB_DECL_AX(12) HB_DECL_AX(13) HB_DEC
 namespace {
 
 // Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups): the
-// autotuner's choices on this part, kept where the winner beat the plain
-// schedule by more than ~2% both at about 2^22 and at about 2^24 local nodes
-// (one-wave workgroups at low degree, D^T in LDS where registers are scarce).
+// autotuner's choices on this part at about 2^24 local nodes per degree (the
+// order-sweep size), kept where the winner beat the plain schedule by more
+// than ~1.5%; D^T in LDS where registers are scarce (FP64 N = 11..14).
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 3, 0, 3, 3, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0},  // FP64
-    {0, 2, 2, 2, 3, 2, 3, 2, 0, 1, 0, 0, 0, 0, 1, 0},  // FP32
+    {0, 1, 3, 1, 3, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0},  // FP64
+    {0, 0, 3, 0, 0, 1, 0, 2, 0, 1, 0, 0, 0, 0, 1, 0},  // FP32
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};

@@ -6,10 +6,12 @@ nx, ny, nz, N, jitter, mesh_seed, rhs_seed and lam (for example
 `inputs.serving_trace`).  Time starts when the loop starts; a request's
 latency is its completion time minus its arrival time, so it includes queueing.
 Both loops solve every request to the same relative residual and fail loudly on
-any request that does not reach it.
+any request that does not reach it.  Progress lines (every `progress` completed
+requests) go to stderr.
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -61,7 +63,8 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
                 lat.append(time.perf_counter() - t0 - waiting.pop(t))
                 iters += res.iters
                 if progress and len(lat) % progress == 0:
-                    print(f"  engine: {len(lat)}/{len(trace)} done at {time.perf_counter() - t0:.1f} s", flush=True)
+                    print(f"  engine: {len(lat)}/{len(trace)} done at {time.perf_counter() - t0:.1f} s",
+                          file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
     finally:
         eng.close()
@@ -94,5 +97,6 @@ def replay_sequential(trace, *, rtol=1e-8, max_iter=200000, progress=None):
         lat.append(time.perf_counter() - t0 - arrival)
         iters += res.iters
         if progress and len(lat) % progress == 0:
-            print(f"  sequential: {len(lat)}/{len(trace)} done at {time.perf_counter() - t0:.1f} s", flush=True)
+            print(f"  sequential: {len(lat)}/{len(trace)} done at {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
     return _summary(lat, time.perf_counter() - t0, iters)
