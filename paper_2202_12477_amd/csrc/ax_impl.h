@@ -10,14 +10,16 @@
 //   - the rows of D a thread needs live in registers (reused by every layer),
 //     and so do its columns unless the schedule puts D^T in LDS;
 //     D[c][*] is uniform across the block and comes through the scalar cache;
-//   - each block holds EPB elements (EPB*(N+1)^2 <= 256 threads), so N=7 is
-//     one wave per element and low orders pack several elements per wave.
+//   - each workgroup holds EPB elements (EPB*(N+1)^2 <= 256 threads, or <= 64
+//     under the one-wave schedule), so N=7 is one wave per element and low
+//     orders pack several elements per wave.
 // HBM streams: map (4 B/node) and the 7 geometric values once, coalesced per
 // layer (G non-temporal, two layers ahead; stored layer-major per element, so
-// an element's factors are one sequential 56(N+1)^3-byte read); x through an indirect
+// an element's factors are one sequential read); x through an indirect
 // (cache-friendly) gather; y by device-scope atomic adds into a zeroed vector
 // (atomics on every node: mixing plain stores into lines that other elements
-// update atomically measured far slower).
+// update atomically measured far slower), with face-shared nodes of
+// neighbouring elements in one wave merged first.
 //
 // T is the arithmetic type: double (the method's FP64 operator) or float (the
 // FP32 operator of the mixed-precision solver: FP32 geometry and D, x rounded

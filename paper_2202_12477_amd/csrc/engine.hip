@@ -144,9 +144,9 @@ class BatchRunner {
         if (run.empty()) return HB_OK;
         max_quota = std::max(max_quota, 1);
         if ((dirty_ || max_quota != built_quota_) && (st = build_lists(run, max_quota))) return st;
-        const int sub_iters = iters * top_mult_;
-        for (int j = 0; j < sub_iters; ++j) {
-            const int need = j / iters + 1;  // multiplier a problem needs to run sub-iteration j
+        const int64_t sub_iters = static_cast<int64_t>(iters) * top_mult_;
+        for (int64_t j = 0; j < sub_iters; ++j) {
+            const int need = static_cast<int>(j / iters) + 1;  // multiplier a problem needs to run sub-iteration j
             for (const Class &c : classes_) {
                 const int n = count_at(c.levels, need);
                 if (n > 0 && (st = launch_batch_ax(c.N, c.D, c.fp32, items_ + c.off, n, probs_, s_))) return st;
