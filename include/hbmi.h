@@ -269,20 +269,21 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 
 /* ------------------------------------------------------------------------ */
 /* Operator tile schedules and their autotuner.                              */
-/* The operator (single, CG and batched launches) runs one of up to four     */
-/* compiled tile schedules per (degree, precision) class: bit 0 reads the    */
-/* columns of D for the divergence from LDS instead of registers; bit 1 uses */
-/* one-wave workgroups (available for N <= 7, where an element fits in a     */
-/* wave) instead of 256-thread workgroups.  The choice changes the reduction */
-/* grouping of p.Ap and the order of assembly atomics only (results agree to */
-/* rounding).  The table is process-wide, starts from measured defaults, and */
+/* The operator (single, CG and batched launches) runs one of four compiled */
+/* tile schedules per (degree, precision) class: bit 0 (1) reads the        */
+/* columns of D for the divergence from LDS instead of registers; bit 1 (2)  */
+/* uses one-wave workgroups instead of 256-thread workgroups (N <= 7, where  */
+/* an element fits in a wave); bit 2 (4) keeps no f_t array and targets two  */
+/* waves per SIMD (N >= 8).  The choice changes the reduction grouping of    */
+/* p.Ap, the order of assembly atomics and of the t-part sums only (results  */
+/* agree to rounding).  The table is process-wide, starts from measured defaults, and */
 /* must not be changed while solves are in flight.  `prec`: HB_PREC_FP64     */
 /* selects the FP64 operator's entry, either mixed precision the FP32 one.   */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t schedule;   /* the schedule chosen (now in the table) */
     int32_t candidates; /* schedules timed */
-    double us[4];       /* mean launch time per schedule in microseconds; < 0: not available at this degree */
+    double us[8];       /* mean launch time per schedule value in microseconds; < 0: not available here */
 } hb_tune_result;
 
 /* Current schedule of a class. */

@@ -23,14 +23,14 @@ HB_DECL_AX(9) HB_DECL_AX(10) HB_DECL_AX(11) HB_DECL_AX(12) HB_DECL_AX(13) HB_DEC
 
 namespace {
 
-// Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups): the
-// autotuner's choices on this part at about 2^24 local nodes per degree (the
-// order-sweep size), kept where the winner beat the plain schedule by more
-// than ~1.5%; D^T in LDS where registers are scarce (FP64 N = 11..14).
+// Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups, N <= 7;
+// bit 2: lean registers with two waves per SIMD, N >= 8): the autotuner's
+// choices on this part at about 2^24 local nodes per degree (the order-sweep
+// size), kept where the winner beat the plain schedule by more than ~1.5%.
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 1, 3, 1, 3, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 0},  // FP64
-    {0, 0, 3, 0, 0, 1, 0, 2, 0, 1, 0, 0, 0, 0, 1, 0},  // FP32
+    {0, 1, 3, 1, 3, 0, 0, 3, 0, 0, 0, 1, 5, 5, 5, 5},  // FP64
+    {0, 0, 3, 0, 0, 1, 0, 2, 0, 1, 1, 0, 0, 0, 1, 0},  // FP32
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};
@@ -56,7 +56,9 @@ int ax_schedule(int N, bool fp32)
 
 bool ax_schedule_legal(int N, int v)
 {
-    return N >= 1 && N <= kMaxN && v >= 0 && v < kNumSched && (!(v & kSchedWave) || (N + 1) * (N + 1) <= 64);
+    const bool small = (N + 1) * (N + 1) <= 64;  // an element fits in a wave
+    return N >= 1 && N <= kMaxN && v >= 0 && v < kNumSched && (!(v & kSchedWave) || small) &&
+           (!(v & kSchedLean) || !small);
 }
 
 void set_ax_schedule(int N, bool fp32, int v)

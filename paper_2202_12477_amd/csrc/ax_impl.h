@@ -52,9 +52,14 @@ __device__ inline gptr<T> to_global(T *p)
 //                   keeping them in registers (frees 2(N+1) registers);
 //   kSchedWave    - one-wave workgroups of floor(64/(N+1)^2) elements instead of
 //                   256-thread workgroups: no element spans two waves, so the
-//                   per-layer barriers are wave-local (legal for N <= 7).
+//                   per-layer barriers are wave-local (legal for N <= 7);
+//   kSchedLean    - no f_t array (the t-part of D^T is added per layer) and a
+//                   target of two waves per SIMD, for the high degrees whose
+//                   registers otherwise allow one (legal for N >= 8).
 template <int N>
 constexpr bool kWaveLegal = (N + 1) * (N + 1) <= 64;
+template <int N>
+constexpr bool kLeanLegal = !kWaveLegal<N>;
 
 template <int N, int V = 0>
 struct AxShape {
@@ -149,7 +154,14 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
 #pragma unroll
         for (int f = 0; f < kGeo; ++f) Gq[p][f] = __builtin_nontemporal_load(&ge[(p * kGeo + f) * np2]);
     }
-    T ft[n1], yv[n1];
+    // lean schedule: the t-part of D^T is added into the column as each layer's
+    // f_t appears, so no f_t array is kept (2(N+1) fewer registers)
+    constexpr bool lean = (V & kSchedLean) != 0;
+    T ft[lean ? 1 : n1], yv[n1];
+    if constexpr (lean) {
+#pragma unroll
+        for (int c = 0; c < n1; ++c) yv[c] = 0;
+    }
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
         // keep each layer's instructions together: stops the scheduler from
@@ -177,8 +189,15 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
         }
         const T fr = G[0] * qr + G[1] * qs + G[2] * qt;
         const T fs = G[1] * qr + G[3] * qs + G[4] * qt;
-        ft[c] = G[2] * qr + G[4] * qs + G[5] * qt;
-        pin(ft[c]);
+        if constexpr (lean) {
+            T f = G[2] * qr + G[4] * qs + G[5] * qt;
+            pin(f);
+#pragma unroll
+            for (int k = 0; k < n1; ++k) yv[k] += Dm[c * n1 + k] * f;
+        } else {
+            ft[c] = G[2] * qr + G[4] * qs + G[5] * qt;
+            pin(ft[c]);
+        }
         T acc = lambda * G[6] * q[c];
         if (lane_used) {
             sr[el][ab] = fr;
@@ -194,16 +213,21 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             for (int m = 0; m < n1; ++m) acc += DaT[m] * sr[el][b * n1 + m] + DbT[m] * ss[el][m * n1 + a];
         }
         pin(acc);
-        yv[c] = acc;
+        if constexpr (lean)
+            yv[c] += acc;
+        else
+            yv[c] = acc;
     }
     __builtin_amdgcn_sched_barrier(0);
-    // t-part of D^T from registers
+    if constexpr (!lean) {
+        // t-part of D^T from registers
 #pragma unroll
-    for (int c = 0; c < n1; ++c) {
-        T s = 0;
+        for (int c = 0; c < n1; ++c) {
+            T s = 0;
 #pragma unroll
-        for (int m = 0; m < n1; ++m) s += Dm[m * n1 + c] * ft[m];
-        yv[c] += s;
+            for (int m = 0; m < n1; ++m) s += Dm[m * n1 + c] * ft[m];
+            yv[c] += s;
+        }
     }
     // assemble through Z^T.  Where several elements share a wave, the a = 0 face
     // node of an element is the a = N face node of the previous one whenever the
@@ -246,7 +270,8 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
 }
 
 template <int N, bool DOT, typename T, int V>
-__global__ __launch_bounds__((AxShape<N, V>::threads)) void ax_kernel(
+__global__ __launch_bounds__((AxShape<N, V>::threads))
+__attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
     int64_t E, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm, T lambda,
     const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st)
 {
@@ -284,7 +309,8 @@ __device__ inline double uniform(double v)
 // class share it; as a read-only kernel argument its block-uniform entries come
 // through scalar loads.
 template <int N, typename T, int V>
-__global__ __launch_bounds__((AxShape<N, V>::threads)) void batch_ax_kernel(const WorkItem *__restrict__ items,
+__global__ __launch_bounds__((AxShape<N, V>::threads))
+__attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void batch_ax_kernel(const WorkItem *__restrict__ items,
                                                                          const BatchProb *__restrict__ probs,
                                                                          const T *__restrict__ Dm)
 {
@@ -312,21 +338,24 @@ int ax_grid(int64_t E)
     return static_cast<int>((E + AxShape<N, V>::epb - 1) / AxShape<N, V>::epb);
 }
 
-// Run-time schedule -> compile-time instantiation.  A schedule with one-wave
-// workgroups at a degree where an element does not fit in a wave maps to the
-// same schedule without them.
+// Run-time schedule -> compile-time instantiation.  Bits not available at
+// this degree are dropped (the host validates schedules before they reach
+// the table, so this only bounds the instantiations).
+template <int N>
+constexpr int legal_sched(int v)
+{
+    return v & (kSchedColsLds | (kWaveLegal<N> ? kSchedWave : 0) | (kLeanLegal<N> ? kSchedLean : 0));
+}
 template <int N, typename F>
 decltype(auto) with_schedule(int v, F &&f)
 {
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, kWaveLegal<N> ? 2 : 0>;
-    using I3 = std::integral_constant<int, kWaveLegal<N> ? 3 : 1>;
-    switch (v) {
-    case 1: return f(I1{});
-    case 2: return f(I2{});
-    case 3: return f(I3{});
-    default: return f(I0{});
+    switch (legal_sched<N>(v)) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, legal_sched<N>(2)>{});
+    case 3: return f(std::integral_constant<int, legal_sched<N>(3)>{});
+    case 4: return f(std::integral_constant<int, legal_sched<N>(4)>{});
+    case 5: return f(std::integral_constant<int, legal_sched<N>(5)>{});
+    default: return f(std::integral_constant<int, 0>{});
     }
 }
 

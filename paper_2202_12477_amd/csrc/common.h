@@ -13,8 +13,9 @@
 namespace hb {
 
 constexpr int kMaxN = 15;
-// Operator tile schedules (bit flags): D^T read from LDS; one-wave workgroups.
-constexpr int kSchedColsLds = 1, kSchedWave = 2, kNumSched = 4;
+// Operator tile schedules (bit flags): D^T read from LDS; one-wave workgroups
+// (N <= 7); lean registers with two waves per SIMD (N >= 8).
+constexpr int kSchedColsLds = 1, kSchedWave = 2, kSchedLean = 4, kNumSched = 8;
 constexpr int kGeo = 7;  // G_rr, G_rs, G_rt, G_ss, G_st, G_tt, c
 
 // Thread-local error message behind hb_last_error().

@@ -107,7 +107,7 @@ hb_status hb_autotune(int32_t N, int32_t prec, int64_t local_nodes, int32_t reps
     const int prev = ax_schedule(N, fp32);
     hb_tune_result res{};
     res.schedule = prev;
-    for (int v = 0; v < 4; ++v) res.us[v] = -1.0;
+    for (double &u : res.us) u = -1.0;
     double best_us = std::numeric_limits<double>::infinity();
     for (int v = 0; v < kNumSched; ++v) {
         if (!ax_schedule_legal(N, v)) continue;

@@ -43,7 +43,7 @@ def relerr(a, b):
 
 
 def legal(N):
-    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1]
+    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5]
 
 
 @pytest.fixture(autouse=True)
@@ -103,11 +103,11 @@ def test_cg_history_under_schedule(v):
     m.close()
 
 
-def test_batch_under_wave_schedules_matches_default():
+def test_batch_under_other_schedules_matches_default():
     cases = [inputs.BoxCase("s1", 3, 2, 2, 1, 0.05, 1, 21), inputs.BoxCase("s3", 4, 3, 2, 3, 0.05, 2, 22),
              inputs.BoxCase("s5", 2, 2, 3, 5, 0.05, 3, 23), inputs.BoxCase("s7", 3, 2, 2, 7, 0.05, 4, 24),
              inputs.BoxCase("s9", 2, 2, 2, 9, 0.05, 5, 25)]
-    say("[case] batch FP64 under one-wave schedules vs default")
+    say("[case] batch FP64 under one-wave / lean schedules vs default")
 
     def run():
         ms, bs, xs = [], [], []
@@ -127,7 +127,7 @@ def test_batch_under_wave_schedules_matches_default():
 
     x0, r0 = run()
     for c in cases:
-        hb.set_schedule(c.N, hb.PREC_FP64, 3 if (c.N + 1) ** 2 <= 64 else 1)
+        hb.set_schedule(c.N, hb.PREC_FP64, 3 if (c.N + 1) ** 2 <= 64 else 5)
     x1, r1 = run()
     for c, a, b, ra, rb in zip(cases, x0, x1, r0, r1):
         assert ra.iters == rb.iters == 60, c.name
