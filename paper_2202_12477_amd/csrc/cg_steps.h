@@ -11,6 +11,26 @@ namespace hb {
 
 constexpr int kFinThreads = 1024;
 
+// Fixed-order sum of partial[0..n) by one block (call from every thread).
+// The partials were written by an earlier kernel on the stream.
+__device__ inline double sum_partials(const double *partial, int n, double *scratch)
+{
+    // eight loads in flight per thread, added in index order (the same sums as a
+    // plain strided loop, without waiting on each load)
+    double s = 0.0;
+    const int step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * step < n; i += 8 * step) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = partial[i + k * step];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; i < n; i += step) s += partial[i];
+    return block_sum(s, scratch);
+}
+
 // Start of iteration j = it + 1: alpha = rho_j / p.Ap, or stop on breakdown
 // (p.Ap <= 0 or not finite), or apply a stop decided by the previous beta.
 __device__ inline void alpha_step(const double *__restrict__ partial, int nblk, CgState *st,

@@ -30,15 +30,6 @@ __device__ inline double block_sum(double v, double *scratch)
     return s;
 }
 
-// Fixed-order sum of partial[0..n) by one block (call from every thread).
-// The partials were written by an earlier kernel on the stream.
-__device__ inline double sum_partials(const double *partial, int n, double *scratch)
-{
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
-    return block_sum(s, scratch);
-}
-
 // Workgroups are dispatched to the 8 XCDs of the device in turn (id mod 8).
 // Give each XCD a contiguous range of tiles so that tiles sharing data
 // (neighbouring elements) are served by the same L2.  A bijection on [0, n).
