@@ -138,7 +138,15 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
     T q[n1];
     gptr<const uint32_t> me = (gptr<const uint32_t>)map + eo * np3 + ab;
 #pragma unroll
-    for (int c = 0; c < n1; ++c) idx[c] = me[c * np2];
+    for (int c = 0; c < n1; ++c) {
+        // inside CG (DOT) the vector kernels evict everything between operator
+        // calls, and a non-temporal map stream keeps p and Ap in the caches;
+        // back to back, the map itself is reused from the last-level cache
+        if constexpr (DOT)
+            idx[c] = __builtin_nontemporal_load(&me[c * np2]);
+        else
+            idx[c] = me[c * np2];
+    }
 #pragma unroll
     for (int c = 0; c < n1; ++c) q[c] = static_cast<T>(x[idx[c]]);
 
