@@ -43,7 +43,7 @@ typedef enum {
     HB_ERR_NOT_CONVERGED = 4, /* tolerance not met within max_iter (results are still filled) */
     HB_ERR_BREAKDOWN = 5,     /* p.Ap <= 0 or not finite during CG */
     HB_ERR_NONFINITE = 6,     /* the initial residual r0.r0 is NaN or Inf */
-    HB_ERR_BUDGET = 7,        /* reserved: request larger than a memory budget */
+    HB_ERR_BUDGET = 7,        /* an engine request larger than the engine's whole memory budget */
     HB_ERR_BUSY = 8           /* reserved */
 } hb_status;
 
@@ -91,11 +91,13 @@ typedef struct {
 
 /* Build the mesh on the device: GLL nodes/weights and the 1D derivative
  * matrix D (NekBone section), the scatter map Z as int32 [E][(N+1)^3], and the
- * geometric factors G_rr, G_rs, G_rt, G_ss, G_st, G_tt and c as FP64
- * [E][7][(N+1)^3] (G_dd' = w_a w_b w_c J sum_i dxi_d/dx_i dxi_d'/dx_i, the
- * metric tensor combined with the GLL weights).  With HB_MESH_FP32 the mesh
- * also keeps the factors and D rounded once to FP32 (28 more bytes per local
- * node).  Synchronises `stream`.
+ * geometric factors G_rr, G_rs, G_rt, G_ss, G_st, G_tt and c in FP64
+ * (G_dd' = w_a w_b w_c J sum_i dxi_d/dx_i dxi_d'/dx_i, the metric tensor
+ * combined with the GLL weights), 56 bytes per local node, stored per element
+ * layer by layer ([E][N+1][7][(N+1)^2]) so the operator reads each element's
+ * factors as one sequential stream (hb_mesh_export returns [E][7][(N+1)^3]).
+ * With HB_MESH_FP32 the mesh also keeps the factors and D rounded once to FP32
+ * (28 more bytes per local node).  Synchronises `stream`.
  * Errors: HB_ERR_INVALID_ARG (bad desc, N_G or N_L >= 2^31, non-positive
  * Jacobian), HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE.  *out is NULL on failure. */
 hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out);
@@ -143,16 +145,17 @@ hb_status hb_ax_f32(hb_mesh mesh, double lambda, const double *dev_x, float *dev
 /* Options of hb_cg_solve (Algorithm 1). */
 typedef struct {
     int32_t max_iter;    /* FP64: iteration cap (>= 0), in fixed mode the exact count;
-                            FP32_IR: cap on the total inner iterations */
+                            FP32_IR / FP32_RR: cap on the CG iterations in total */
     int32_t fixed_iters; /* 1: run exactly max_iter iterations (the benchmark's 100); 0: stop on rtol.
-                            FP32_IR requires 0. */
+                            the mixed modes require 0. */
     double rtol;         /* FP64: stop once ||r_j|| <= rtol ||b|| (recursive residual);
-                            FP32_IR: stop once ||b - A x|| <= rtol ||b|| with the FP64 operator */
+                            FP32_IR / FP32_RR: stop once ||b - A x|| <= rtol ||b|| with the FP64 operator */
     int32_t x0_zero;     /* 1: ignore dev_x on entry and start from x0 = 0 (r0 = b, no operator call) */
     int32_t check_every; /* tolerance mode: read the device state back every this many iterations (<=0: 25) */
     int32_t prec;        /* hb_prec */
-    int32_t max_outer;   /* FP32_IR: cap on refinement steps (<=0: 60) */
-    double inner_rtol;   /* FP32_IR: each inner solve stops at ||r_in|| <= inner_rtol ||r|| (<=0: 1e-3) */
+    int32_t max_outer;   /* FP32_IR: cap on refinement steps (<=0: 60); FP32_RR: cap on replacements (<=0: none) */
+    double inner_rtol;   /* FP32_IR: inner solves reduce ||r|| by this factor; FP32_RR: replace the residual
+                            each time the recursive ||r|| has dropped by this factor (<=0: 1e-3) */
     int32_t graph_k;     /* hb_cg_solve: > 0 enqueues the iterations as replays of one captured HIP graph of
                             graph_k iterations (cached per mesh for the same lambda, x and precision; a replay
                             past the stop is a no-op on the device); 0: one launch per kernel. Ignored by
@@ -160,13 +163,13 @@ typedef struct {
 } hb_cg_opts;
 
 typedef struct {
-    int32_t iters;       /* FP64: iterations completed; FP32_IR: inner iterations in total */
+    int32_t iters;       /* CG iterations completed (FP32_IR: inner iterations in total) */
     int32_t status;      /* hb_status of the solve */
     double res0;         /* ||r_0|| */
-    double res;          /* FP64: ||r_iters|| (recursive); FP32_IR: ||b - A x|| (FP64 operator) at exit */
+    double res;          /* FP64: ||r_iters|| (recursive); mixed: ||b - A x|| (FP64 operator) at exit */
     double bnorm;        /* ||b|| */
-    int32_t outer_iters; /* FP32_IR: refinement steps taken (0 in FP64 mode) */
-    int32_t fp64_iters;  /* FP32_IR: FP64 CG iterations run after the refinement stalled (0 if it did not) */
+    int32_t outer_iters; /* FP32_IR: refinement steps; FP32_RR: replacements (0 in FP64 mode) */
+    int32_t fp64_iters;  /* mixed: FP64 CG iterations run after the FP32 operator stalled (0 if it did not) */
 } hb_cg_result;
 
 /* Algorithm 1 on the assembled system A x = b: r0 = b - A x0, p = r0; per
@@ -261,7 +264,9 @@ hb_status hb_engine_destroy(hb_engine engine);
 hb_status hb_engine_submit(hb_engine engine, const hb_mesh_desc *desc, double lambda, uint64_t rhs_seed, double rtol,
                            uint64_t *ticket);
 /* Admit, run `iters` iterations (<= 0: the engine default) of every admitted
- * request, retire finished ones.  info may be NULL.  Synchronises the stream. */
+ * request (cheaper requests up to max_quota times as many, see
+ * hb_engine_opts), retire finished ones.  info may be NULL.  Synchronises the
+ * stream. */
 hb_status hb_engine_step(hb_engine engine, int32_t iters, hb_engine_info *info);
 /* *done = 1 and the results (host_x: N_G doubles, may be NULL) if the request
  * has finished; the engine then forgets it.  *done = 0 otherwise. */
@@ -276,9 +281,10 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 /* an element fits in a wave); bit 2 (4) keeps no f_t array and targets two  */
 /* waves per SIMD (N >= 8).  The choice changes the reduction grouping of    */
 /* p.Ap, the order of assembly atomics and of the t-part sums only (results  */
-/* agree to rounding).  The table is process-wide, starts from measured defaults, and */
-/* must not be changed while solves are in flight.  `prec`: HB_PREC_FP64     */
-/* selects the FP64 operator's entry, either mixed precision the FP32 one.   */
+/* agree to rounding).  The table is process-wide, starts from measured      */
+/* defaults, and must not be changed while solves are in flight.  `prec`:    */
+/* HB_PREC_FP64 selects the FP64 operator's entry, either mixed precision    */
+/* the FP32 one.                                                             */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t schedule;   /* the schedule chosen (now in the table) */
