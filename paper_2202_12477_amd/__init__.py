@@ -34,10 +34,10 @@ PREC_FP32_RR = 2
 
 # Every entry point of include/hbmi.h, in declaration order.
 EXPORTS = (
-    "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax",
-    "hb_ax_add", "hb_ax_f32", "hb_cg_solve", "hb_batch_solve", "hb_engine_footprint", "hb_engine_create",
-    "hb_engine_destroy", "hb_engine_submit", "hb_engine_step", "hb_engine_poll", "hb_stream_probe",
-    "hb_status_string", "hb_last_error", "hb_get_schedule", "hb_set_schedule", "hb_autotune",
+    "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax", "hb_ax_add",
+    "hb_ax_f32", "hb_cg_solve", "hb_batch_solve", "hb_engine_footprint", "hb_engine_create", "hb_engine_destroy",
+    "hb_engine_submit", "hb_engine_step", "hb_engine_poll", "hb_get_schedule", "hb_set_schedule", "hb_autotune",
+    "hb_stream_probe", "hb_status_string", "hb_last_error",
 )
 
 
