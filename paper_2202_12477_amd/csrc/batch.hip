@@ -6,7 +6,10 @@
 // problems.  Each problem keeps its own device state (CgState), so problems
 // at different iterations, or already finished, share the same launches
 // (finished ones return at once).  The host rebuilds the work lists only when
-// the set of running problems changes.
+// the set of running problems changes.  This file holds the vector and scalar
+// steps; the batched operator kernel is instantiated with the single-problem
+// operator, per degree range (ax_impl.h, ax_n*.hip), and launched through the
+// schedule table (ax.hip).
 #include "ax_impl.h"
 #include "cg_steps.h"
 #include "common.h"
