@@ -30,7 +30,7 @@ AX_CALLS = 50
 CG_ITERS = 100
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ax_f64_box32_N7_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_12477_amd", "csrc", f) for f in ("ax_impl.h", "reduce.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_12477_amd", "csrc", f) for f in ("ax_impl.h", "reduce.h", "walk.h")]
 
 
 def kernel_hash() -> str:

@@ -14,7 +14,8 @@ namespace hb {
     hb_status launch_ax32_##n(const hb_mesh_s *, double, const double *, float *, double *, CgState *,          \
                               hipStream_t);                                                                     \
     hb_status launch_batch_ax_##n(const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t);   \
-    int ax_grid_##n(int64_t, int);
+    int ax_grid_##n(int64_t, int);                                                                              \
+    int ax_epb_##n(int);
 HB_DECL_AX(1) HB_DECL_AX(2) HB_DECL_AX(3) HB_DECL_AX(4) HB_DECL_AX(5) HB_DECL_AX(6) HB_DECL_AX(7) HB_DECL_AX(8)
 HB_DECL_AX(9) HB_DECL_AX(10) HB_DECL_AX(11) HB_DECL_AX(12) HB_DECL_AX(13) HB_DECL_AX(14) HB_DECL_AX(15)
 #undef HB_DECL_AX
@@ -29,7 +30,7 @@ namespace {
 // size), kept where the winner beat the plain schedule by more than ~1.5%.
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 1, 3, 1, 3, 0, 0, 3, 0, 0, 0, 1, 5, 5, 5, 5},  // FP64
+    {0, 1, 3, 1, 3, 0, 0, 3, 0, 0, 0, 1, 4, 5, 5, 5},  // FP64
     {0, 0, 3, 0, 0, 1, 0, 2, 0, 1, 1, 0, 0, 0, 1, 0},  // FP32
 };
 
@@ -115,6 +116,17 @@ int ax_grid_for(int N, int64_t E, int sched)
         HB_ALL_N(HB_CASE)
 #undef HB_CASE
     default: return 0;
+    }
+}
+
+TileWalk ax_walk_for(int N, int64_t nx, int64_t ny, int64_t nz, int sched)
+{
+    switch (N) {
+#define HB_CASE(n) \
+    case n: return make_walk(nx, ny, nz, ax_epb_##n(sched));
+        HB_ALL_N(HB_CASE)
+#undef HB_CASE
+    default: return TileWalk{};
     }
 }
 

@@ -30,6 +30,7 @@
 
 #include "common.h"
 #include "reduce.h"
+#include "walk.h"
 
 namespace hb {
 
@@ -212,7 +213,22 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             ss[el][ab] = fs;
         }
         __syncthreads();
-        if constexpr (cols_lds) {
+        if constexpr (sizeof(T) == 8) {
+            // FP64: the r half, then the s half.  Issued together, the two
+            // halves' LDS operands are the register peak of the kernel (at N=7
+            // the difference between two and three waves per SIMD).
+            if constexpr (cols_lds) {
+#pragma unroll
+                for (int m = 0; m < n1; ++m) acc += sDt[a * n1 + m] * sr[el][b * n1 + m];
+#pragma unroll
+                for (int m = 0; m < n1; ++m) acc += sDt[b * n1 + m] * ss[el][m * n1 + a];
+            } else {
+#pragma unroll
+                for (int m = 0; m < n1; ++m) acc += DaT[m] * sr[el][b * n1 + m];
+#pragma unroll
+                for (int m = 0; m < n1; ++m) acc += DbT[m] * ss[el][m * n1 + a];
+            }
+        } else if constexpr (cols_lds) {
 #pragma unroll
             for (int m = 0; m < n1; ++m)
                 acc += sDt[a * n1 + m] * sr[el][b * n1 + m] + sDt[b * n1 + m] * ss[el][m * n1 + a];
@@ -280,14 +296,15 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
 template <int N, bool DOT, typename T, int V>
 __global__ __launch_bounds__((AxShape<N, V>::threads))
 __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
-    int64_t E, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm, T lambda,
-    const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial, const CgState *__restrict__ st)
+    int64_t E, TileWalk walk, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm,
+    T lambda, const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial,
+    const CgState *__restrict__ st)
 {
     if constexpr (DOT) {
         // stopped, or stopping at the next alpha step (which reads no partials)
         if (st->done | st->pending) return;
     }
-    ax_tile<N, DOT, T, V>(E, xcd_remap(blockIdx.x, gridDim.x), to_global(map), to_global(geo), to_global(Dm),
+    ax_tile<N, DOT, T, V>(E, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), to_global(map), to_global(geo), to_global(Dm),
                           lambda, to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));
 }
 
@@ -373,6 +390,12 @@ int ax_grid_sched(int64_t E, int v)
     return with_schedule<N>(v, [&](auto VV) { return ax_grid<N, decltype(VV)::value>(E); });
 }
 
+template <int N>
+int ax_epb_sched(int v)
+{
+    return with_schedule<N>(v, [&](auto VV) { return AxShape<N, decltype(VV)::value>::epb; });
+}
+
 template <int N, typename T>
 hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambda, const double *x, T *y,
                       double *partial, CgState *st, hipStream_t s)
@@ -382,12 +405,13 @@ hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambd
         const int grid = ax_grid<N, V>(m->E);
         if (grid == 0) return HB_OK;
         const T lam = static_cast<T>(lambda);
+        const TileWalk walk = make_walk(m->desc.nx, m->desc.ny, m->desc.nz, AxShape<N, V>::epb);
         if (st)
-            ax_kernel<N, true, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y,
-                                                                             partial, st);
+            ax_kernel<N, true, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
+                                                                             y, partial, st);
         else
-            ax_kernel<N, false, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, m->map, geo, D, lam, x, y,
-                                                                              nullptr, nullptr);
+            ax_kernel<N, false, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
+                                                                              y, nullptr, nullptr);
         HB_HIP(hipGetLastError());
         return HB_OK;
     });
@@ -434,4 +458,5 @@ hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int
         return launch_batch_ax_n<n>(D, fp32, it, ni, pr, s);                                                   \
     }                                                                                                          \
     int ax_grid_##n(int64_t E, int v) { return ax_grid_sched<n>(E, v); }                                       \
+    int ax_epb_##n(int v) { return ax_epb_sched<n>(v); }                                                       \
     }

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "hbmi.h"
+#include "walk.h"
 
 namespace hb {
 
@@ -82,6 +83,7 @@ struct BatchProb {
     CgState *st;
     int64_t E, NG;
     int32_t N, ax_tiles, vec_chunks, use32;  // use32: the operator of this problem is the FP32 one
+    int32_t nx, ny, nz;                      // the box (host side: the order of the operator tiles)
 };
 
 // A unit of batched work: problem index and tile (operator) or chunk (vectors).
@@ -162,6 +164,8 @@ hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float 
 int ax_blocks(const hb_mesh_s *m, bool fp32);
 int ax_blocks_max(const hb_mesh_s *m);
 int ax_grid_for(int N, int64_t E, int sched);
+// The order of the operator's tiles on an nx x ny x nz box under a schedule.
+TileWalk ax_walk_for(int N, int64_t nx, int64_t ny, int64_t nz, int sched);
 // Schedule table (per degree and precision), shared by every solve path.
 int ax_schedule(int N, bool fp32);
 bool ax_schedule_legal(int N, int sched);

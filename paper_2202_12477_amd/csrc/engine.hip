@@ -119,6 +119,9 @@ class BatchRunner {
         P.E = m->E;
         P.NG = m->NG;
         P.N = m->N;
+        P.nx = m->desc.nx;
+        P.ny = m->desc.ny;
+        P.nz = m->desc.nz;
         P.ax_tiles = ax_blocks(m, mixed);  // recomputed with the lists (schedule, precision)
         P.vec_chunks = static_cast<int32_t>((m->NG + kBatchChunk - 1) / kBatchChunk);
         P.use32 = mixed ? 1 : 0;
@@ -289,7 +292,10 @@ class BatchRunner {
                     const BatchProb &P = h_probs_[i];
                     if (P.N != N || P.use32 != f) continue;
                     c.D = f ? static_cast<const void *>(P.D32) : static_cast<const void *>(P.D);
-                    for (int t = 0; t < P.ax_tiles; ++t) h_items_[nit++] = WorkItem{i, t};
+                    // the single-problem launch's tile order (locality of the shared lines)
+                    const TileWalk w = ax_walk_for(P.N, P.nx, P.ny, P.nz, ax_schedule(P.N, f != 0));
+                    for (int t = 0; t < P.ax_tiles; ++t)
+                        h_items_[nit++] = WorkItem{i, static_cast<int32_t>(walk_tile(w, static_cast<uint32_t>(t)))};
                     c.levels.push_back(Level{mult_[i], nit - c.off});
                 }
                 if (!c.levels.empty()) classes_.push_back(std::move(c));

@@ -135,7 +135,7 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
     # measured defaults (autotuner at 2^24 local nodes), D^T from LDS for FP64 N = 11..14
-    fp64 = [1, 3, 1, 3, 0, 0, 3, 0, 0, 0, 1, 5, 5, 5, 5]
+    fp64 = [1, 3, 1, 3, 0, 0, 3, 0, 0, 0, 1, 4, 5, 5, 5]
     fp32 = [0, 3, 0, 0, 1, 0, 2, 0, 1, 1, 0, 0, 0, 1, 0]
     for N in range(1, 16):
         assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
