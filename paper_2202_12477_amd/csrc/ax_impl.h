@@ -14,8 +14,9 @@
 //     under the one-wave schedule), so N=7 is one wave per element and low
 //     orders pack several elements per wave.
 // HBM streams: map (4 B/node) and the 7 geometric values once, coalesced per
-// layer (G non-temporal, two layers ahead; stored layer-major per element, so
-// an element's factors are one sequential read); x through an indirect
+// layer (G two layers ahead, non-temporal where an element's run of a factor
+// fills a cache line; stored layer-major per element, so an element's factors
+// are one sequential read); x through an indirect
 // (cache-friendly) gather; y by device-scope atomic adds into a zeroed vector
 // (atomics on every node: mixing plain stores into lines that other elements
 // update atomically measured far slower), with face-shared nodes of
@@ -82,6 +83,20 @@ template <typename T>
 __device__ inline void pin(T &v)
 {
     asm volatile("" : "+v"(v));
+}
+
+// Geometry loads.  Non-temporal where one element's run of a factor within a
+// layer ((N+1)^2 values) fills at least a 128-byte line; below that (FP64 N <= 2,
+// FP32 N <= 4) a load instruction touches many partial lines that the next
+// factors' loads touch again, and plain loads, which keep the lines in L2 for
+// them, measured up to 1.6x faster.
+template <bool NT, typename T>
+__device__ inline T geo_load(gptr<const T> p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 template <typename T>
@@ -152,16 +167,17 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
     for (int c = 0; c < n1; ++c) q[c] = static_cast<T>(x[idx[c]]);
 
     // G is streamed once: non-temporal loads keep it from evicting x and y from
-    // the caches.  Layers c+1 .. c+PF are in flight while layer c is computed
+    // the caches (above a line per element and factor, geo_load).  Layers c+1 .. c+PF are in flight while layer c is computed
     // (a ring of PF register sets; the loop is unrolled, so slots are static).
     constexpr int PF = kPrefetch < n1 ? kPrefetch : n1;
     // geometry layout [E][layer c][factor f][(N+1)^2 nodes of the layer]
     gptr<const T> ge = geo + eo * kGeo * np3 + ab;
+    constexpr bool geo_nt = np2 * sizeof(T) >= 128;
     T Gq[PF][kGeo];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
 #pragma unroll
-        for (int f = 0; f < kGeo; ++f) Gq[p][f] = __builtin_nontemporal_load(&ge[(p * kGeo + f) * np2]);
+        for (int f = 0; f < kGeo; ++f) Gq[p][f] = geo_load<geo_nt>(&ge[(p * kGeo + f) * np2]);
     }
     // lean schedule: the t-part of D^T is added into the column as each layer's
     // f_t appears, so no f_t array is kept (2(N+1) fewer registers)
@@ -182,7 +198,7 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
         if (c + PF < n1) {
 #pragma unroll
             for (int f = 0; f < kGeo; ++f)
-                Gq[c % PF][f] = __builtin_nontemporal_load(&ge[((c + PF) * kGeo + f) * np2]);
+                Gq[c % PF][f] = geo_load<geo_nt>(&ge[((c + PF) * kGeo + f) * np2]);
         }
         // t-derivative from registers; D[c][*] is uniform (scalar loads)
         T qt = 0;
