@@ -158,8 +158,10 @@ typedef struct {
                             each time the recursive ||r|| has dropped by this factor (<=0: 1e-3) */
     int32_t graph_k;     /* hb_cg_solve: > 0 enqueues the iterations as replays of one captured HIP graph of
                             graph_k iterations (cached per mesh for the same lambda, x and precision; a replay
-                            past the stop is a no-op on the device); 0: one launch per kernel. Ignored by
-                            hb_batch_solve. */
+                            past the stop is a no-op on the device); 0: one launch per kernel.
+                            hb_batch_solve: > 0 makes each segment graph_k iterations long (instead of
+                            check_every) and replays it from a captured graph until the set of running
+                            problems changes. At most 4096. */
 } hb_cg_opts;
 
 typedef struct {
@@ -244,6 +246,8 @@ typedef struct {
     int32_t max_quota;      /* iteration quota per step: a request whose iteration costs at most 1/2^k of
                                the costliest running request's advances 2^k times the step's iterations,
                                capped at max_quota (<= 0: 64; 1: every request advances equally) */
+    int32_t graphs;         /* 1: a step's launches are replays of a captured HIP graph, re-captured whenever
+                               the set of running requests (or the step length) changes; 0: plain launches */
 } hb_engine_opts;
 
 typedef struct {

@@ -61,7 +61,7 @@ class _MeshInfo(ctypes.Structure):
 class _EngineOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("iters_per_step", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("max_quota", ctypes.c_int32)]
+                ("max_quota", ctypes.c_int32), ("graphs", ctypes.c_int32)]
 
 
 class _EngineInfo(ctypes.Structure):
@@ -284,8 +284,9 @@ class Mesh:
 
 def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool = False, rtol: float = 1e-8,
                 x0_zero: bool = True, check_every: int = 0, prec: int = PREC_FP64, inner_rtol: float = 0.0,
-                stream=None, raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
-    """Solve independent problems together (hb_batch_solve); returns (status, [CgResult])."""
+                graph_k: int = 0, stream=None, raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
+    """Solve independent problems together (hb_batch_solve); returns (status, [CgResult]).
+    graph_k > 0: segments of graph_k iterations replayed from captured graphs."""
     import torch
 
     n = len(meshes)
@@ -299,7 +300,7 @@ def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool 
     B = (ctypes.c_void_p * n)(*[_ptr(b, torch.float64) for b in bs])
     X = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64) for x in xs])
     R = (_CgResult * n)()
-    opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, 0, inner_rtol, 0)
+    opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, 0, inner_rtol, graph_k)
     st = lib().hb_batch_solve(n, H, L, B, X, ctypes.byref(opts), R, _stream(stream))
     if st in raise_on:
         _check(st, "hb_batch_solve")
@@ -318,8 +319,9 @@ class Engine:
     """Continuous-batching serving engine (hb_engine_*)."""
 
     def __init__(self, hbm_budget: int, max_slots: int, prec: int = PREC_FP32_RR, max_iter: int = 100000,
-                 iters_per_step: int = 25, inner_rtol: float = 0.0, max_quota: int = 0, stream=None):
-        o = _EngineOpts(hbm_budget, max_slots, prec, max_iter, iters_per_step, inner_rtol, max_quota)
+                 iters_per_step: int = 25, inner_rtol: float = 0.0, max_quota: int = 0, graphs: bool = False,
+                 stream=None):
+        o = _EngineOpts(hbm_budget, max_slots, prec, max_iter, iters_per_step, inner_rtol, max_quota, int(graphs))
         h = ctypes.c_void_p()
         self._stream = _stream(stream)
         _check(lib().hb_engine_create(ctypes.byref(o), self._stream, ctypes.byref(h)), "hb_engine_create")

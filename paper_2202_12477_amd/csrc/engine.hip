@@ -34,6 +34,8 @@ class BatchRunner {
     BatchRunner(int capacity, hipStream_t s) : cap_(capacity), s_(s) {}
     ~BatchRunner()
     {
+        if (gexec_) (void)hipGraphExecDestroy(gexec_);
+        if (cap_s_) (void)hipStreamDestroy(cap_s_);
         for (void *p : {(void *)probs_, (void *)states_, (void *)items_, (void *)plist_, (void *)norms_})
             if (p) (void)hipFree(p);
         for (void *p : {(void *)h_probs_, (void *)h_states_, (void *)h_items_, (void *)h_plist_, (void *)h_norms_,
@@ -146,23 +148,24 @@ class BatchRunner {
             if (slots_[i].used && !slots_[i].finished) run.push_back(i);
         if (run.empty()) return HB_OK;
         max_quota = std::max(max_quota, 1);
-        if ((dirty_ || max_quota != built_quota_) && (st = build_lists(run, max_quota))) return st;
-        const int64_t sub_iters = static_cast<int64_t>(iters) * top_mult_;
-        for (int64_t j = 0; j < sub_iters; ++j) {
-            const int need = static_cast<int>(j / iters) + 1;  // multiplier a problem needs to run sub-iteration j
-            for (const Class &c : classes_) {
-                const int n = count_at(c.levels, need);
-                if (n > 0 && (st = launch_batch_ax(c.N, c.D, c.fp32, items_ + c.off, n, probs_, s_))) return st;
-            }
-            const int nrun = count_at(run_levels_, need), nvec = count_at(vec_levels_, need);
-            if ((st = launch_batch_alpha(plist_, nrun, probs_, s_)) ||
-                (st = launch_batch_residual(items_ + vec_off_, nvec, probs_, s_)) ||
-                (st = launch_batch_beta(plist_, nrun, probs_, s_)) ||
-                (st = launch_batch_update(items_ + vec_off_, nvec, probs_, s_)))
-                return st;
+        // the lists depend on the running set, the quotas and the schedule
+        // table (tile counts and order): rebuilt when any of them changed
+        if ((dirty_ || max_quota != built_quota_ || ax_schedule_epoch() != built_epoch_) &&
+            (st = build_lists(run, max_quota)))
+            return st;
+        if (graphs_) {
+            hipGraphExec_t g = nullptr;
+            if ((st = step_graph(iters, &g))) return st;
+            HB_HIP(hipGraphLaunch(g, s_));
+        } else if ((st = enqueue_step(iters, s_))) {
+            return st;
         }
         return handle_stops(run);
     }
+
+    // Replay each step's launches from a captured graph (rebuilt whenever the
+    // lists or the step length change).
+    void use_graphs(bool on) { graphs_ = on; }
 
   private:
     struct Slot {
@@ -186,6 +189,62 @@ class BatchRunner {
         const void *D;              // the class's derivative matrix (any of its meshes)
         std::vector<Level> levels;  // items of the class's problems, by multiplier (descending)
     };
+    // The launches of one step: `iters` iterations of every running problem
+    // (times its quota multiplier), on stream s.
+    hb_status enqueue_step(int iters, hipStream_t s)
+    {
+        hb_status st;
+        const int64_t sub_iters = static_cast<int64_t>(iters) * top_mult_;
+        for (int64_t j = 0; j < sub_iters; ++j) {
+            const int need = static_cast<int>(j / iters) + 1;  // multiplier a problem needs to run sub-iteration j
+            for (const Class &c : classes_) {
+                const int n = count_at(c.levels, need);
+                if (n > 0 && (st = launch_batch_ax(c.N, c.D, c.fp32, items_ + c.off, n, probs_, s))) return st;
+            }
+            const int nrun = count_at(run_levels_, need), nvec = count_at(vec_levels_, need);
+            if ((st = launch_batch_alpha(plist_, nrun, probs_, s)) ||
+                (st = launch_batch_residual(items_ + vec_off_, nvec, probs_, s)) ||
+                (st = launch_batch_beta(plist_, nrun, probs_, s)) ||
+                (st = launch_batch_update(items_ + vec_off_, nvec, probs_, s)))
+                return st;
+        }
+        return HB_OK;
+    }
+
+    // The step as an executable graph: the cached one if the lists and the
+    // step length are unchanged, else captured on a private stream (every
+    // launch of a step is a kernel, so the graph holds kernel nodes only).
+    hb_status step_graph(int iters, hipGraphExec_t *out)
+    {
+        if (gexec_ && g_iters_ == iters && g_version_ == lists_version_) {
+            *out = gexec_;
+            return HB_OK;
+        }
+        if (gexec_) {
+            (void)hipGraphExecDestroy(gexec_);
+            gexec_ = nullptr;
+        }
+        if (!cap_s_) HB_HIP(hipStreamCreateWithFlags(&cap_s_, hipStreamNonBlocking));
+        HB_HIP(hipStreamBeginCapture(cap_s_, hipStreamCaptureModeThreadLocal));
+        const hb_status st = enqueue_step(iters, cap_s_);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(cap_s_, &graph);
+        if (st != HB_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st != HB_OK ? st : hip_fail(e, "hipStreamEndCapture");
+        }
+        const hipError_t ei = hipGraphInstantiate(&gexec_, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            gexec_ = nullptr;
+            return hip_fail(ei, "hipGraphInstantiate");
+        }
+        g_iters_ = iters;
+        g_version_ = lists_version_;
+        *out = gexec_;
+        return HB_OK;
+    }
+
     static int count_at(const std::vector<Level> &levels, int need)
     {
         int n = 0;
@@ -257,6 +316,8 @@ class BatchRunner {
         // enqueued kernels may still read the previous lists and copies the
         // host staging: wait before rewriting either
         HB_HIP(hipStreamSynchronize(s_));
+        built_epoch_ = ax_schedule_epoch();  // read before the schedules themselves
+        ++lists_version_;
         // operator tiles under the current schedule of each problem's class
         // (sets the list lengths, so before sizing the lists)
         for (int i : run) {
@@ -391,8 +452,14 @@ class BatchRunner {
     std::vector<Class> classes_;
     std::vector<Level> vec_levels_, run_levels_;
     std::vector<int> mult_;
-    int vec_off_ = 0, top_mult_ = 1, built_quota_ = 0;
+    int vec_off_ = 0, top_mult_ = 1, built_quota_ = 0, built_epoch_ = -1;
     bool dirty_ = true;
+    // graph replay of steps
+    bool graphs_ = false;
+    hipStream_t cap_s_ = nullptr;
+    hipGraphExec_t gexec_ = nullptr;
+    int g_iters_ = 0;
+    uint64_t lists_version_ = 0, g_version_ = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -470,6 +537,8 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
     if (opts->max_iter < 0) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: max_iter must be >= 0");
     if (mixed && fixed) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: mixed precision needs a tolerance");
     if (!fixed && !(opts->rtol >= 0.0)) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: rtol must be >= 0");
+    if (opts->graph_k < 0 || opts->graph_k > 4096)
+        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: graph_k must be in [0, 4096]");
     for (int i = 0; i < nprob; ++i) {
         if (!meshes[i] || !dev_b[i] || !dev_x[i] || dev_b[i] == dev_x[i])
             return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": bad pointers");
@@ -488,7 +557,11 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
     if ((st = runner.init())) return st;
     for (int i = 0; i < nprob; ++i)
         if ((st = runner.add(i, meshes[i], lambdas[i], dev_b[i], dev_x[i], *opts))) return st;
-    const int chunk = fixed ? std::max(opts->max_iter, 1) : (opts->check_every > 0 ? opts->check_every : 25);
+    int chunk = fixed ? std::max(opts->max_iter, 1) : (opts->check_every > 0 ? opts->check_every : 25);
+    if (opts->graph_k > 0) {
+        chunk = fixed ? std::min(chunk, opts->graph_k) : opts->graph_k;
+        runner.use_graphs(true);
+    }
     do {
         if ((st = runner.step(chunk))) return st;
     } while (runner.running() > 0);
@@ -524,6 +597,7 @@ hb_status hb_engine_create(const hb_engine_opts *opts, void *stream, hb_engine *
     e->opts = *opts;
     e->s = static_cast<hipStream_t>(stream);
     e->runner.reset(new (std::nothrow) BatchRunner(opts->max_slots, e->s));
+    if (e->runner) e->runner->use_graphs(opts->graphs != 0);
     e->active.resize(opts->max_slots);
     hb_status st = e->runner ? e->runner->init() : fail(HB_ERR_OUT_OF_MEMORY, "hb_engine_create: host allocation");
     if (st) {

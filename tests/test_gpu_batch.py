@@ -84,12 +84,30 @@ def test_batch_fp64_matches_oracle_history_end():
         assert compare_history(got[: k + 1], href[: k + 1], bar[: k + 1]) <= 1.0, c.name
 
 
-@pytest.mark.parametrize("prec", [hb.PREC_FP64, hb.PREC_FP32_RR])
-def test_batch_tolerance_solves(prec):
-    say(f"[case] batch tolerance prec={prec}")
+def test_batch_graph_replay_matches_single_solves():
+    """Segments replayed from captured graphs (16 iterations, which does not
+    divide the 60: the device stops each problem at its cap) give the one-by-one
+    solves' results."""
+    say("[case] batch FP64 fixed 60 iterations, graph_k=16, vs one-by-one")
+    ms, bs, xs = setup(SMALL)
+    st, res = hb.batch_solve(ms, [c.lam for c in SMALL], bs, xs, max_iter=60, fixed_iters=True, graph_k=16)
+    assert st == hb.HB_OK
+    for c, m, b, x, r in zip(SMALL, ms, bs, xs, res):
+        x1 = torch.empty_like(b)
+        r1 = m.cg(c.lam, b, x1, max_iter=60, fixed_iters=True)
+        assert r.iters == r1.iters == 60 and r.status == r1.status, c.name
+        xb, xs1 = host(x), host(x1)
+        assert np.linalg.norm(xb - xs1) <= 1e-9 * np.linalg.norm(xs1), c.name
+        assert r.res == pytest.approx(r1.res, rel=1e-8)
+
+
+@pytest.mark.parametrize("prec,graph_k", [(hb.PREC_FP64, 0), (hb.PREC_FP32_RR, 0), (hb.PREC_FP64, 10),
+                                          (hb.PREC_FP32_RR, 10)])
+def test_batch_tolerance_solves(prec, graph_k):
+    say(f"[case] batch tolerance prec={prec} graph_k={graph_k}")
     ms, bs, xs = setup(SMALL, fp32=True)
     st, res = hb.batch_solve(ms, [c.lam for c in SMALL], bs, xs, max_iter=5000, rtol=1e-9, prec=prec,
-                             check_every=10)
+                             check_every=10, graph_k=graph_k)
     assert st == hb.HB_OK, [r.status for r in res]
     for c, x, r in zip(SMALL, xs, res):
         ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
@@ -123,5 +141,8 @@ def test_batch_argument_errors():
         hb.batch_solve(ms, [1.0, 1.0], bs, xs, prec=hb.PREC_FP32_RR)
     with pytest.raises(hb.HbError):
         hb.batch_solve(ms, [1.0, -1.0], bs, xs)
+    for k in (-1, 4097):
+        with pytest.raises(hb.HbError):
+            hb.batch_solve(ms, [1.0, 1.0], bs, xs, graph_k=k)
     st, res = hb.batch_solve([], [], [], [])
     assert st == hb.HB_OK and res == []

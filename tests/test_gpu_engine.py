@@ -45,13 +45,14 @@ def alone(c, prec):
     return x.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", [hb.PREC_FP64, hb.PREC_FP32_RR])
-def test_engine_mix_equals_alone(prec):
-    say(f"[case] engine prec={prec}")
+@pytest.mark.parametrize("prec,graphs", [(hb.PREC_FP64, False), (hb.PREC_FP32_RR, False), (hb.PREC_FP64, True),
+                                         (hb.PREC_FP32_RR, True)])
+def test_engine_mix_equals_alone(prec, graphs):
+    say(f"[case] engine prec={prec} graphs={graphs}")
     # a budget for about three of the larger requests at a time forces queueing
     fps = [hb.request_footprint(c.nx, c.ny, c.nz, c.N, prec, 100000) for c in REQS]
     budget = 3 * max(fps)
-    eng = hb.Engine(budget, max_slots=4, prec=prec, max_iter=100000, iters_per_step=20)
+    eng = hb.Engine(budget, max_slots=4, prec=prec, max_iter=100000, iters_per_step=20, graphs=graphs)
     tickets = {}
     results = {}
     saw_queue = False
@@ -92,6 +93,46 @@ def test_engine_mix_equals_alone(prec):
         assert tr <= 1.2 * TOL
         assert d <= 2.2 * TOL
     eng.close()
+
+
+def test_engine_follows_a_schedule_change_between_steps():
+    """Changing a class's tile schedule while requests are admitted: the engine
+    rebuilds its work lists (tile counts and order) before the next step."""
+    say("[case] engine schedule change between steps")
+    cases = [REQS[4], REQS[5], REQS[3]]  # N = 7, 9, 3
+    old = {c.N: hb.get_schedule(c.N, hb.PREC_FP64) for c in cases}
+    new = {7: 0 if old[7] != 0 else 3, 9: 1 if old[9] != 1 else 0, 3: 2 if old[3] != 2 else 1}
+    eng = hb.Engine(8 << 30, max_slots=4, prec=hb.PREC_FP64, max_iter=100000, iters_per_step=5, graphs=True)
+    try:
+        tickets = {eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, rhs_seed=c.rhs_seed,
+                              rtol=TOL): c for c in cases}
+        eng.step()
+        eng.step()
+        for N, v in new.items():
+            hb.set_schedule(N, hb.PREC_FP64, v)
+        results = {}
+        for _ in range(100000):
+            if len(results) == len(cases):
+                break
+            eng.step()
+            for t in tickets:
+                if t not in results:
+                    out = eng.poll(t)
+                    if out is not None:
+                        results[t] = out
+        assert len(results) == len(cases)
+    finally:
+        for N, v in old.items():
+            hb.set_schedule(N, hb.PREC_FP64, v)
+        eng.close()
+    for t, c in tickets.items():
+        r, x = results[t]
+        assert r.status == hb.HB_OK, (c.name, r)
+        ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+        bh = oracle.rhs(ref.NG, c.rhs_seed)
+        tr = np.linalg.norm(bh - ref.ax(x, c.lam)) / np.linalg.norm(bh)
+        say(f"{c.name}: iters {r.iters} true residual {tr:.2e}")
+        assert tr <= 1.2 * TOL
 
 
 def test_engine_rejects_requests_larger_than_budget():
