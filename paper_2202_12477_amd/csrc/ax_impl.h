@@ -16,11 +16,13 @@
 // HBM streams: map (4 B/node) and the 7 geometric values once, coalesced per
 // layer (G two layers ahead, non-temporal where an element's run of a factor
 // fills a cache line; stored layer-major per element, so an element's factors
-// are one sequential read); x through an indirect
-// (cache-friendly) gather; y by device-scope atomic adds into a zeroed vector
-// (atomics on every node: mixing plain stores into lines that other elements
-// update atomically measured far slower), with face-shared nodes of
-// neighbouring elements in one wave merged first.
+// are one sequential read); x through an indirect (cache-friendly) gather; y
+// by device-scope atomic adds into a zeroed vector (atomics on every node:
+// mixing plain stores into lines that other elements update atomically
+// measured far slower), with face-shared nodes of neighbouring elements in one
+// wave merged first.  On a box the tiles are visited in a walk that keeps each
+// XCD's neighbouring elements close in time (walk.h), so the lines of x and y
+// they share meet in that XCD's L2.
 //
 // T is the arithmetic type: double (the method's FP64 operator) or float (the
 // FP32 operator of the mixed-precision solver: FP32 geometry and D, x rounded
