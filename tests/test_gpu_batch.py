@@ -146,3 +146,29 @@ def test_batch_argument_errors():
             hb.batch_solve(ms, [1.0, 1.0], bs, xs, graph_k=k)
     st, res = hb.batch_solve([], [], [], [])
     assert st == hb.HB_OK and res == []
+
+
+def test_batched_workload_full_size():
+    """The 64-problem batched workload at its full size, solved as the benchmark
+    solves it (FP32 operator with FP64 residual replacement, to 1e-8): every
+    problem's true residual, computed with the oracle's FP64 operator, meets the
+    tolerance."""
+    cases = inputs.batched_cases()
+    say(f"[case] batched workload, {len(cases)} problems, FP32 RR to 1e-8")
+    ms, bs, xs = setup(cases, fp32=True)
+    st, res = hb.batch_solve(ms, [c.lam for c in cases], bs, xs, max_iter=100000, rtol=1e-8,
+                             prec=hb.PREC_FP32_RR)
+    assert st == hb.HB_OK, [r.status for r in res]
+    for m in ms:
+        m.close()
+    worst = 0.0
+    for i, (c, x, r) in enumerate(zip(cases, xs, res)):
+        ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+        bh = oracle.rhs(ref.NG, c.rhs_seed)
+        tr = np.linalg.norm(bh - ref.ax(host(x), c.lam)) / np.linalg.norm(bh)
+        del ref
+        worst = max(worst, tr)
+        if i % 8 == 0:
+            say(f"{i}: {c.name} iters {r.iters} replacements {r.outer_iters} true residual {tr:.2e}")
+        assert r.status == hb.HB_OK and tr <= 1.2e-8, (c.name, r, tr)
+    say(f"worst true residual {worst:.2e}")

@@ -160,3 +160,47 @@ def test_request_loops_replay_a_trace():
         assert r["requests"] == 4 and r["solves_per_s"] > 0 and r["cg_iterations"] > 0
         assert 0 < r["p50_s"] <= r["p99_s"] <= r["wall_s"]
     assert a["engine_steps"] >= 1
+
+
+def test_serving_workload_full_size():
+    """The first 48 arrivals of the serving trace at their full sizes (up to 40M
+    local nodes per request), through the engine configured as in the serving
+    measurement (FP32 operator with FP64 residual replacement, 64 GB budget, 32
+    slots, 25 iterations per step, quotas).  Every request must finish with its
+    FP64 true residual (computed on the device by the engine) within 1e-8; the
+    requests the oracle handles in about a second (up to 5M local nodes) are
+    checked again with the oracle's FP64 operator."""
+    trace = inputs.serving_trace(48)
+    say(f"[case] serving workload, {len(trace)} requests at full size")
+    eng = hb.Engine(64 << 30, max_slots=32, prec=hb.PREC_FP32_RR, max_iter=200000, iters_per_step=25)
+    try:
+        tickets = {eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, rhs_seed=c.rhs_seed,
+                              lam=c.lam, rtol=TOL): c for _, c in trace}
+        results = {}
+        steps = 0
+        while len(results) < len(tickets):
+            eng.step()
+            steps += 1
+            for t, c in tickets.items():
+                if t not in results:
+                    out = eng.poll(t)
+                    if out is not None:
+                        results[t] = out
+                        if len(results) % 8 == 0:
+                            say(f"{len(results)} done after {steps} steps")
+            assert steps < 200000
+    finally:
+        eng.close()
+    checked = 0
+    for t, c in tickets.items():
+        r, x = results[t]
+        assert r.status == hb.HB_OK, (c.name, r)
+        assert r.res <= TOL * r.bnorm * 1.0000001, (c.name, r.res / r.bnorm)
+        if c.nx * c.ny * c.nz * (c.N + 1) ** 3 <= 5_000_000:
+            ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+            bh = oracle.rhs(ref.NG, c.rhs_seed)
+            tr = np.linalg.norm(bh - ref.ax(x, c.lam)) / np.linalg.norm(bh)
+            assert tr <= 1.2 * TOL, (c.name, tr)
+            checked += 1
+    say(f"{checked} of {len(tickets)} requests checked against the oracle")
+    assert checked >= 40
