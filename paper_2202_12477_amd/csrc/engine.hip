@@ -4,7 +4,9 @@
 // advances all of them together (one operator launch per (degree, precision)
 // class, one launch per vector/scalar step; see batch.hip).  Problems join
 // between segments of iterations and leave as soon as they finish, so work
-// that arrives while others run is overlapped with them.
+// that arrives while others run is overlapped with them.  A segment's launches
+// can be replayed from a captured HIP graph, re-captured whenever the running
+// set (and with it the work lists) changes.
 //
 // The engine puts a request queue in front of it: a request (box mesh, degree,
 // lambda, forcing seed, tolerance) is admitted first-in first-out when a slot
