@@ -165,3 +165,49 @@ def test_autotune_needs_device(L):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     assert L.hb_autotune(3, 0, 0, 5, None, None) == hb.HB_ERR_DEVICE
+
+
+STRUCTS = {"hb_mesh_desc": "_MeshDesc", "hb_mesh_info": "_MeshInfo", "hb_cg_opts": "_CgOpts",
+           "hb_cg_result": "_CgResult", "hb_engine_opts": "_EngineOpts", "hb_engine_info": "_EngineInfo",
+           "hb_tune_result": "_TuneResult"}
+
+
+@pytest.mark.skipif(__import__("shutil").which("gcc") is None, reason="no host C compiler")
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every option/result struct of the binding has the C header's size and
+    field offsets (compiled with the host C compiler)."""
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "hbmi.h"', 'int main(void) {']
+    for c, py in STRUCTS.items():
+        lines.append(f'    printf("{c} size %zu\\n", sizeof({c}));')
+        for name, _ in getattr(hb, py)._fields_:
+            lines.append(f'    printf("{c} {name} %zu\\n", offsetof({c}, {name}));')
+    lines += ['    return 0;', '}']
+    src, exe = tmp_path / "layout.c", tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        c, name, v = line.split()
+        got[(c, name)] = int(v)
+    for c, py in STRUCTS.items():
+        cls = getattr(hb, py)
+        assert got[(c, "size")] == ctypes.sizeof(cls), c
+        for name, _ in cls._fields_:
+            assert got[(c, name)] == getattr(cls, name).offset, (c, name)
+
+
+def header_fields(struct):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + struct + r"\s*;", text).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            names += [re.sub(r"\[.*\]", "", v).strip(" *") for v in decl.split(" ", 1)[1].split(",")]
+    return names
+
+
+def test_binding_structs_have_every_header_field():
+    for c, py in STRUCTS.items():
+        assert header_fields(c) == [n for n, _ in getattr(hb, py)._fields_], c
