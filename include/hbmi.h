@@ -20,7 +20,9 @@
  *  - Assembled vectors have N_G = (nx*N+1)(ny*N+1)(nz*N+1) entries in
  *    lexicographic global order g = I + gx*(J + gy*K), gx = nx*N+1,
  *    gy = ny*N+1, where global node (I,J,K) = (ex*N+a, ey*N+b, ez*N+c) for local
- *    GLL node (a,b,c) of element (ex,ey,ez).  No boundary node is masked.
+ *    GLL node (a,b,c) of element (ex,ey,ez).  No boundary node is masked,
+ *    except on meshes built with HB_MESH_DIRICHLET: there only the interior
+ *    nodes carry DOFs, g = (I-1) + (gx-2)((J-1) + (gy-2)(K-1)).
  *  - A mesh object is not thread-safe: calls on one mesh from several host
  *    threads, or on several streams at once, must be serialised by the caller
  *    (the CG workspace is owned by the mesh).
@@ -55,7 +57,12 @@ typedef enum {
 typedef enum { HB_MASS_GWJ = 0, HB_MASS_INVDEG = 1 } hb_mass;
 
 /* Mesh flags. */
-enum { HB_MESH_FP32 = 1 /* also keep FP32 geometric factors and D, for hb_ax_f32 and FP32 refinement */ };
+enum {
+    HB_MESH_FP32 = 1,     /* also keep FP32 geometric factors and D, for hb_ax_f32 and FP32 refinement */
+    HB_MESH_DIRICHLET = 2 /* homogeneous Dirichlet box (the paper's experiments): the nodes on the boundary of
+                             [0,1]^3 carry no DOF, so N_G = (nx N - 1)(ny N - 1)(nz N - 1), numbered
+                             lexicographically over the interior nodes; needs nx N, ny N, nz N >= 2 */
+};
 
 /* Precision of hb_cg_solve. */
 typedef enum {
@@ -77,7 +84,7 @@ typedef struct {
     double jitter;      /* 0 <= jitter < 0.5 (0: affine box) */
     uint64_t seed;      /* jitter seed */
     int32_t mass;       /* hb_mass */
-    int32_t flags;      /* 0 or HB_MESH_FP32 */
+    int32_t flags;      /* HB_MESH_FP32 | HB_MESH_DIRICHLET, or 0 */
 } hb_mesh_desc;
 
 typedef struct {
@@ -108,7 +115,8 @@ hb_status hb_mesh_destroy(hb_mesh mesh);
 hb_status hb_mesh_query(hb_mesh mesh, hb_mesh_info *info);
 
 /* Copy mesh data to host memory (any pointer may be NULL to skip it):
- * host_geo: 7*N_L doubles, layout [E][7][(N+1)^3]; host_map: N_L int32;
+ * host_geo: 7*N_L doubles, layout [E][7][(N+1)^3]; host_map: N_L int32
+ * (-1 for a boundary node of a HB_MESH_DIRICHLET mesh);
  * host_D: (N+1)^2 doubles row-major, D[i][j] = l_j'(xi_i);
  * host_xi, host_w: N+1 doubles each (GLL nodes ascending, weights).
  * Synchronous. */
@@ -264,7 +272,8 @@ hb_status hb_engine_create(const hb_engine_opts *opts, void *stream, hb_engine *
 /* Releases every device buffer (admitted requests are dropped).  NULL is accepted. */
 hb_status hb_engine_destroy(hb_engine engine);
 /* Queue a request; HB_ERR_BUDGET if its footprint exceeds the whole budget
- * (it could never be admitted).  desc->flags is set by the engine. */
+ * (it could never be admitted).  Of desc->flags only HB_MESH_DIRICHLET is
+ * taken; the engine adds HB_MESH_FP32 itself in mixed precision. */
 hb_status hb_engine_submit(hb_engine engine, const hb_mesh_desc *desc, double lambda, uint64_t rhs_seed, double rtol,
                            uint64_t *ticket);
 /* Admit, run `iters` iterations (<= 0: the engine default) of every admitted

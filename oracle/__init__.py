@@ -55,6 +55,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_deriv.argtypes = [i32, dp, dp]
         L.oracle_vertices.argtypes = [i32, i32, i32, f64, u64, dp]
         L.oracle_map.argtypes = [i32, i32, i32, i32, lp]
+        L.oracle_map_dirichlet.argtypes = [i32, i32, i32, i32, lp]
         L.oracle_geometry.argtypes = [i32, i32, i32, i32, dp, i32, dp]
         L.oracle_ax.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp]
         L.oracle_ax.restype = None
@@ -109,7 +110,9 @@ MASS_INVDEG = 1  # A = S + lambda I   (c = inverse multiplicity W)
 
 @dataclass
 class Mesh:
-    """Box mesh of nx*ny*nz hexahedra of degree N on [0,1]^3 (no masking)."""
+    """Box mesh of nx*ny*nz hexahedra of degree N on [0,1]^3: no masking, or with
+    dirichlet=True homogeneous Dirichlet conditions on the boundary of the box (the
+    boundary nodes carry no DOF; N_G = (nx N - 1)(ny N - 1)(nz N - 1))."""
 
     nx: int
     ny: int
@@ -118,6 +121,7 @@ class Mesh:
     jitter: float = 0.0
     seed: int = 0
     mass: int = MASS_GWJ
+    dirichlet: bool = False
 
     def __post_init__(self):
         L = lib()
@@ -125,12 +129,14 @@ class Mesh:
         self.E = self.nx * self.ny * self.nz
         self.Np = n1 ** 3
         self.NL = self.E * self.Np
-        self.NG = (self.nx * self.N + 1) * (self.ny * self.N + 1) * (self.nz * self.N + 1)
+        k = -1 if self.dirichlet else 1
+        self.NG = (self.nx * self.N + k) * (self.ny * self.N + k) * (self.nz * self.N + k)
         self.xi, self.w = gll(self.N)
         self.D = deriv(self.N)
         self.V = vertices(self.nx, self.ny, self.nz, self.jitter, self.seed)
         self.map = np.empty(self.NL, dtype=np.int64)
-        L.oracle_map(self.nx, self.ny, self.nz, self.N, _p(self.map, ctypes.c_int64))
+        (L.oracle_map_dirichlet if self.dirichlet else L.oracle_map)(self.nx, self.ny, self.nz, self.N,
+                                                                      _p(self.map, ctypes.c_int64))
         self.geo = np.empty(self.E * 7 * self.Np)
         st = L.oracle_geometry(self.nx, self.ny, self.nz, self.N, _p(self.V), self.mass, _p(self.geo))
         if st != 0:

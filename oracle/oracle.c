@@ -204,6 +204,33 @@ void oracle_map(int nx, int ny, int nz, int N, int64_t *map)
             }
 }
 
+/* The same rows for the box with homogeneous Dirichlet conditions on the
+ * boundary of [0,1]^3, as in the paper's experiments (their DOF counts are
+ * (nN-1)^3): a node on the boundary carries no DOF (map entry -1) and the
+ * interior nodes are numbered lexicographically,
+ * (I-1) + (gx-2)((J-1) + (gy-2)(K-1)). */
+void oracle_map_dirichlet(int nx, int ny, int nz, int N, int64_t *map)
+{
+    int n1 = N + 1;
+    int64_t Np = (int64_t)n1 * n1 * n1;
+    int64_t gx = (int64_t)nx * N + 1, gy = (int64_t)ny * N + 1, gz = (int64_t)nz * N + 1;
+    for (int ez = 0; ez < nz; ++ez)
+        for (int ey = 0; ey < ny; ++ey)
+            for (int ex = 0; ex < nx; ++ex) {
+                int64_t e = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+                for (int c = 0; c <= N; ++c)
+                    for (int b = 0; b <= N; ++b)
+                        for (int a = 0; a <= N; ++a) {
+                            int64_t I = (int64_t)ex * N + a;
+                            int64_t J = (int64_t)ey * N + b;
+                            int64_t K = (int64_t)ez * N + c;
+                            int boundary = I == 0 || J == 0 || K == 0 || I == gx - 1 || J == gy - 1 || K == gz - 1;
+                            map[e * Np + a + n1 * (b + n1 * c)] =
+                                boundary ? -1 : (I - 1) + (gx - 2) * ((J - 1) + (gy - 2) * (K - 1));
+                        }
+            }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometric factors (NekBone section: G^e is the symmetric 3x3 block of     */
 /* diagonal matrices holding the metric tensor combined with GLL weights).   */
@@ -308,6 +335,8 @@ int oracle_geometry(int nx, int ny, int nz, int N, const double *V, int mass_kin
 /* with the gradient D = [D (x) I (x) I; I (x) D (x) I; I (x) I (x) D] acting on */
 /* the element's (N+1)^3 nodal values (r along a, s along b, t along c).      */
 /* C is diagonal with the 7th geometric value c (see oracle_geometry).        */
+/* A map entry -1 (a Dirichlet boundary node) has no DOF: Z puts 0 there and  */
+/* Z^T drops its value.                                                       */
 /* ------------------------------------------------------------------------ */
 void oracle_ax(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
                double lambda, const double *x, double *y)
@@ -324,7 +353,7 @@ void oracle_ax(int64_t E, int N, const double *D, const double *geo, const int64
         const int64_t *me = map + e * Np;
         const double *ge = geo + e * 7 * Np;
         /* Z: gather the element's nodal values from the assembled vector */
-        for (int64_t n = 0; n < Np; ++n) q[n] = x[me[n]];
+        for (int64_t n = 0; n < Np; ++n) q[n] = me[n] >= 0 ? x[me[n]] : 0.0;
         /* D: reference gradient */
         for (int c = 0; c <= N; ++c)
             for (int b = 0; b <= N; ++b)
@@ -361,7 +390,8 @@ void oracle_ax(int64_t E, int N, const double *D, const double *geo, const int64
                     ye[n] = s + lambda * ge[6 * Np + n] * q[n];
                 }
         /* Z^T: assemble (gather-sum) into the global vector */
-        for (int64_t n = 0; n < Np; ++n) y[me[n]] += ye[n];
+        for (int64_t n = 0; n < Np; ++n)
+            if (me[n] >= 0) y[me[n]] += ye[n];
     }
 #undef IDX
     free(q); free(qr); free(qs); free(qt); free(fr); free(fs); free(ft); free(ye);

@@ -28,6 +28,7 @@ HB_ERR_BUSY = 8
 MASS_GWJ = 0
 MASS_INVDEG = 1
 MESH_FP32 = 1
+MESH_DIRICHLET = 2
 PREC_FP64 = 0
 PREC_FP32_IR = 1
 PREC_FP32_RR = 2
@@ -183,14 +184,16 @@ class Mesh:
     """A device-resident box mesh (hb_mesh_create / hb_mesh_destroy)."""
 
     def __init__(self, nx: int, ny: int, nz: int, N: int, jitter: float = 0.0, seed: int = 0,
-                 mass: int = MASS_GWJ, fp32: bool = False, stream=None):
-        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, MESH_FP32 if fp32 else 0)
+                 mass: int = MASS_GWJ, fp32: bool = False, dirichlet: bool = False, stream=None):
+        """dirichlet: the boundary nodes of the box carry no DOF (N_G = (nx N - 1)(ny N - 1)(nz N - 1))."""
+        flags = (MESH_FP32 if fp32 else 0) | (MESH_DIRICHLET if dirichlet else 0)
+        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, flags)
         h = ctypes.c_void_p()
         _check(lib().hb_mesh_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)), "hb_mesh_create")
         self._h = h
         info = _MeshInfo()
         _check(lib().hb_mesh_query(h, ctypes.byref(info)), "hb_mesh_query")
-        self.nx, self.ny, self.nz, self.N = nx, ny, nz, N
+        self.nx, self.ny, self.nz, self.N, self.dirichlet = nx, ny, nz, N, dirichlet
         self.E, self.NL, self.NG = info.n_elem, info.n_local, info.n_global
 
     @property
@@ -307,9 +310,10 @@ def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool 
     return st, [CgResult(r.iters, r.status, r.res0, r.res, r.bnorm, r.outer_iters, r.fp64_iters) for r in R]
 
 
-def request_footprint(nx: int, ny: int, nz: int, N: int, prec: int = PREC_FP64, max_iter: int = 100000) -> int:
+def request_footprint(nx: int, ny: int, nz: int, N: int, prec: int = PREC_FP64, max_iter: int = 100000,
+                      dirichlet: bool = False) -> int:
     """Device bytes a request of this size holds while the engine has it admitted."""
-    d = _MeshDesc(nx, ny, nz, N, 0.0, 0, MASS_GWJ, 0)
+    d = _MeshDesc(nx, ny, nz, N, 0.0, 0, MASS_GWJ, MESH_DIRICHLET if dirichlet else 0)
     out = ctypes.c_size_t()
     _check(lib().hb_engine_footprint(ctypes.byref(d), prec, max_iter, ctypes.byref(out)), "hb_engine_footprint")
     return int(out.value)
@@ -339,12 +343,14 @@ class Engine:
         except Exception:
             pass
 
-    def submit(self, nx, ny, nz, N, *, jitter=0.05, seed=0, lam=1.0, rhs_seed=0, rtol=1e-8, mass=MASS_GWJ) -> int:
-        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, 0)
+    def submit(self, nx, ny, nz, N, *, jitter=0.05, seed=0, lam=1.0, rhs_seed=0, rtol=1e-8, mass=MASS_GWJ,
+               dirichlet=False) -> int:
+        d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, MESH_DIRICHLET if dirichlet else 0)
         t = ctypes.c_uint64()
         _check(lib().hb_engine_submit(self._h, ctypes.byref(d), lam, rhs_seed, rtol, ctypes.byref(t)),
                "hb_engine_submit")
-        self._ng[t.value] = (nx * N + 1) * (ny * N + 1) * (nz * N + 1)
+        k = -1 if dirichlet else 1
+        self._ng[t.value] = (nx * N + k) * (ny * N + k) * (nz * N + k)
         return int(t.value)
 
     def step(self, iters: int = 0) -> dict:

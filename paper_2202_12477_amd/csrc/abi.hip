@@ -88,11 +88,13 @@ hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out)
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: element counts must be >= 1");
     if (!(d.jitter >= 0.0 && d.jitter < 0.5)) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: jitter must be in [0, 0.5)");
     if (d.mass != HB_MASS_GWJ && d.mass != HB_MASS_INVDEG) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: bad mass kind");
-    if (d.flags & ~HB_MESH_FP32) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: unknown flag");
+    if (d.flags & ~(HB_MESH_FP32 | HB_MESH_DIRICHLET)) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: unknown flag");
+    if ((d.flags & HB_MESH_DIRICHLET) && ((int64_t)d.nx * d.N < 2 || (int64_t)d.ny * d.N < 2 || (int64_t)d.nz * d.N < 2))
+        return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: a Dirichlet box needs interior nodes (n*N >= 2)");
     const int64_t n1 = d.N + 1;
     const double E_d = (double)d.nx * d.ny * d.nz;
     const double NL_d = E_d * n1 * n1 * n1;
-    const double NG_d = ((double)d.nx * d.N + 1) * ((double)d.ny * d.N + 1) * ((double)d.nz * d.N + 1);
+    const double NG_d = ((double)d.nx * d.N + 1) * ((double)d.ny * d.N + 1) * ((double)d.nz * d.N + 1);  // bound
     if (NL_d >= 2147483647.0 || NG_d >= 2147483647.0)
         return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: local or global node count exceeds the int32 map");
     hb_status st = check_device();
@@ -104,7 +106,7 @@ hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out)
     m->N = d.N;
     m->E = (int64_t)d.nx * d.ny * d.nz;
     m->NL = m->E * n1 * n1 * n1;
-    m->NG = ((int64_t)d.nx * d.N + 1) * ((int64_t)d.ny * d.N + 1) * ((int64_t)d.nz * d.N + 1);
+    m->NG = box_global_nodes(d);
     gll_basis(d.N, m->h_xi, m->h_w, m->h_D);
     hipStream_t s = static_cast<hipStream_t>(stream);
     size_t tally = 0;

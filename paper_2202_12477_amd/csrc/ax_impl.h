@@ -78,6 +78,10 @@ struct AxShape {
 // Geometry layers in flight ahead of the one being computed.
 constexpr int kPrefetch = 2;
 
+// Map entry of a node without a DOF (the boundary of a Dirichlet box): the
+// gather reads 0 there and the assembly skips it.
+constexpr uint32_t kNoDof = 0xffffffffu;
+
 // Materialise a value here: stops the compiler from sinking a layer's
 // arithmetic to the end of the kernel, which would keep every layer's LDS
 // operands live at once.
@@ -166,7 +170,11 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             idx[c] = me[c * np2];
     }
 #pragma unroll
-    for (int c = 0; c < n1; ++c) q[c] = static_cast<T>(x[idx[c]]);
+    for (int c = 0; c < n1; ++c) {
+        const bool dof = idx[c] != kNoDof;
+        const double v = x[dof ? idx[c] : 0u];
+        q[c] = dof ? static_cast<T>(v) : T(0);
+    }
 
     // G is streamed once: non-temporal loads keep it from evicting x and y from
     // the caches (above a line per element and factor, geo_load).  Layers c+1 .. c+PF are in flight while layer c is computed
@@ -293,11 +301,13 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             const T v_next = __shfl(yv[c], lane + kShift);
             const bool recv = may_recv && id_next == id;
             const bool sent = may_send && id_prev == id;
-            if (active && !sent) atomic_add(&y[idx[c]], recv ? yv[c] + v_next : yv[c]);
+            if (active && !sent && id != static_cast<int>(kNoDof))
+                atomic_add(&y[idx[c]], recv ? yv[c] + v_next : yv[c]);
         }
     } else if (active) {
 #pragma unroll
-        for (int c = 0; c < n1; ++c) atomic_add(&y[idx[c]], yv[c]);
+        for (int c = 0; c < n1; ++c)
+            if (idx[c] != kNoDof) atomic_add(&y[idx[c]], yv[c]);
     }
     if constexpr (DOT) {
         // sum_e x_e . y_e = x . Z^T y_L = x . A x, accumulated in FP64

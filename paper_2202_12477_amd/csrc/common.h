@@ -126,6 +126,14 @@ struct CgWork {
 
 }  // namespace hb
 
+// Global nodes (DOFs) of a box mesh: every GLL node of the box, or only the
+// interior ones with HB_MESH_DIRICHLET.
+inline int64_t box_global_nodes(const hb_mesh_desc &d)
+{
+    const int64_t gx = (int64_t)d.nx * d.N + 1, gy = (int64_t)d.ny * d.N + 1, gz = (int64_t)d.nz * d.N + 1;
+    return (d.flags & HB_MESH_DIRICHLET) ? (gx - 2) * (gy - 2) * (gz - 2) : gx * gy * gz;
+}
+
 struct hb_mesh_s {
     hb_mesh_desc desc;
     int N = 0;

@@ -474,7 +474,7 @@ size_t request_footprint(const hb_mesh_desc &d, int prec, int max_iter)
 {
     const double n1 = d.N + 1.0;
     const double NL = (double)d.nx * d.ny * d.nz * n1 * n1 * n1;
-    const double NG = ((double)d.nx * d.N + 1) * ((double)d.ny * d.N + 1) * ((double)d.nz * d.N + 1);
+    const double NG = static_cast<double>(box_global_nodes(d));
     const bool mixed = prec == HB_PREC_FP32_RR;
     double bytes = NL * (4.0 + 8.0 * kGeo) + (mixed ? NL * 4.0 * kGeo : 0.0);  // map, geometry
     bytes += NG * (8.0 * 3 + (mixed ? 4.0 : 0.0));                               // r, p, Ap (+ FP32 Ap)
@@ -627,6 +627,9 @@ hb_status hb_engine_submit(hb_engine e, const hb_mesh_desc *desc, double lambda,
     if (desc->N < 1 || desc->N > kMaxN || desc->nx < 1 || desc->ny < 1 || desc->nz < 1 ||
         !(desc->jitter >= 0.0 && desc->jitter < 0.5) || (desc->mass != HB_MASS_GWJ && desc->mass != HB_MASS_INVDEG))
         return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: bad mesh descriptor");
+    if ((desc->flags & HB_MESH_DIRICHLET) &&
+        ((int64_t)desc->nx * desc->N < 2 || (int64_t)desc->ny * desc->N < 2 || (int64_t)desc->nz * desc->N < 2))
+        return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: a Dirichlet box needs interior nodes (n*N >= 2)");
     if (!(lambda > 0.0) || !std::isfinite(lambda) || !(rtol > 0.0))
         return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: lambda and rtol must be > 0");
     const size_t fp = request_footprint(*desc, e->opts.prec, e->opts.max_iter);
@@ -634,7 +637,7 @@ hb_status hb_engine_submit(hb_engine e, const hb_mesh_desc *desc, double lambda,
         return fail(HB_ERR_BUDGET, "hb_engine_submit: the request needs " + std::to_string(fp) +
                                        " device bytes, more than the whole budget");
     hb_engine_s::Request r{e->next_ticket++, *desc, lambda, rhs_seed, rtol, fp};
-    r.desc.flags = e->opts.prec == HB_PREC_FP32_RR ? HB_MESH_FP32 : 0;
+    r.desc.flags = (desc->flags & HB_MESH_DIRICHLET) | (e->opts.prec == HB_PREC_FP32_RR ? HB_MESH_FP32 : 0);
     e->queue.push_back(r);
     *ticket = r.ticket;
     return HB_OK;

@@ -62,7 +62,8 @@ __global__ void vertex_kernel(int nx, int ny, int nz, double jitter, uint64_t sx
 // One thread per local node: Z row, Jacobian of the trilinear map, G and c.
 __global__ void geometry_kernel(int nx, int ny, int nz, int N, const double *__restrict__ V,
                                 const double *__restrict__ xi, const double *__restrict__ w, int mass_invdeg,
-                                int32_t *__restrict__ map, double *__restrict__ geo, int *__restrict__ bad)
+                                int dirichlet, int32_t *__restrict__ map, double *__restrict__ geo,
+                                int *__restrict__ bad)
 {
     const int n1 = N + 1;
     const int64_t np3 = (int64_t)n1 * n1 * n1;
@@ -74,8 +75,14 @@ __global__ void geometry_kernel(int nx, int ny, int nz, int N, const double *__r
     const int a = n % n1, b = (n / n1) % n1, c = n / (n1 * n1);
     const int ex = static_cast<int>(e % nx), ey = static_cast<int>((e / nx) % ny), ez = static_cast<int>(e / ((int64_t)nx * ny));
 
-    const int64_t gx = (int64_t)nx * N + 1, gy = (int64_t)ny * N + 1;
-    map[t] = static_cast<int32_t>((int64_t)(ex * N + a) + gx * ((int64_t)(ey * N + b) + gy * (int64_t)(ez * N + c)));
+    const int64_t gx = (int64_t)nx * N + 1, gy = (int64_t)ny * N + 1, gz = (int64_t)nz * N + 1;
+    const int64_t gi = (int64_t)ex * N + a, gj = (int64_t)ey * N + b, gk = (int64_t)ez * N + c;
+    if (!dirichlet)
+        map[t] = static_cast<int32_t>(gi + gx * (gj + gy * gk));
+    else if (gi == 0 || gj == 0 || gk == 0 || gi == gx - 1 || gj == gy - 1 || gk == gz - 1)
+        map[t] = -1;  // boundary node: no DOF
+    else
+        map[t] = static_cast<int32_t>((gi - 1) + (gx - 2) * ((gj - 1) + (gy - 2) * (gk - 1)));
 
     // Trilinear map x(r) = sum over corners of X_corner * prod_d (1 +- r_d)/2.
     const double r = xi[a], s = xi[b], tt = xi[c];
@@ -130,7 +137,7 @@ __global__ void geometry_kernel(int nx, int ny, int nz, int N, const double *__r
 __global__ void count_kernel(int64_t nl, const int32_t *__restrict__ map, int32_t *__restrict__ mult)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t < nl) atomicAdd(&mult[map[t]], 1);
+    if (t < nl && map[t] >= 0) atomicAdd(&mult[map[t]], 1);
 }
 
 __global__ void invdeg_kernel(int64_t nl, int64_t np3, int64_t np2, const int32_t *__restrict__ map,
@@ -139,7 +146,8 @@ __global__ void invdeg_kernel(int64_t nl, int64_t np3, int64_t np2, const int32_
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= nl) return;
     const int64_t e = t / np3, n = t - e * np3, c = n / np2;
-    geo[(e * np3 + c * np2) * kGeo + 6 * np2 + (n - c * np2)] = 1.0 / static_cast<double>(mult[map[t]]);
+    const int32_t g = map[t];
+    geo[(e * np3 + c * np2) * kGeo + 6 * np2 + (n - c * np2)] = g >= 0 ? 1.0 / static_cast<double>(mult[g]) : 0.0;
 }
 
 inline unsigned blocks_for(int64_t n, int threads) { return static_cast<unsigned>((n + threads - 1) / threads); }
@@ -182,7 +190,9 @@ hb_status build_geometry(hb_mesh_s *m, hipStream_t s)
                                                            sm64(d.seed, 2), sm64(d.seed, 3), V);
         if ((e = hipGetLastError()) != hipSuccess) { st = hip_fail(e, "vertex_kernel"); break; }
         geometry_kernel<<<blocks_for(m->NL, 256), 256, 0, s>>>(d.nx, d.ny, d.nz, m->N, V, m->xi, m->w,
-                                                                 d.mass == HB_MASS_INVDEG, m->map, m->geo, bad);
+                                                                 d.mass == HB_MASS_INVDEG,
+                                                                 (d.flags & HB_MESH_DIRICHLET) != 0, m->map, m->geo,
+                                                                 bad);
         if ((e = hipGetLastError()) != hipSuccess) { st = hip_fail(e, "geometry_kernel"); break; }
         if (d.mass == HB_MASS_INVDEG) {
             if ((e = hipMalloc(&mult, sizeof(int32_t) * m->NG)) != hipSuccess) {
