@@ -14,6 +14,11 @@ namespace hb {
     hb_status launch_ax32_##n(const hb_mesh_s *, double, const double *, float *, double *, CgState *,          \
                               hipStream_t);                                                                     \
     hb_status launch_batch_ax_##n(const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t);   \
+    hb_status launch_ax_d_##n(const hb_mesh_s *, double, const double *, double *, double *, CgState *,         \
+                              hipStream_t);                                                                     \
+    hb_status launch_ax32_d_##n(const hb_mesh_s *, double, const double *, float *, double *, CgState *,        \
+                                hipStream_t);                                                                   \
+    hb_status launch_batch_ax_d_##n(const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t); \
     int ax_grid_##n(int64_t, int);                                                                              \
     int ax_epb_##n(int);
 HB_DECL_AX(1) HB_DECL_AX(2) HB_DECL_AX(3) HB_DECL_AX(4) HB_DECL_AX(5) HB_DECL_AX(6) HB_DECL_AX(7) HB_DECL_AX(8)
@@ -74,9 +79,10 @@ int ax_schedule_epoch() { return g_epoch.load(); }
 hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
                     hipStream_t s)
 {
+    const bool d = (m->desc.flags & HB_MESH_DIRICHLET) != 0;
     switch (m->N) {
 #define HB_CASE(n) \
-    case n: return launch_ax_##n(m, lambda, x, y, partial, st, s);
+    case n: return d ? launch_ax_d_##n(m, lambda, x, y, partial, st, s) : launch_ax_##n(m, lambda, x, y, partial, st, s);
         HB_ALL_N(HB_CASE)
 #undef HB_CASE
     default: return fail(HB_ERR_INVALID_ARG, "unsupported degree N");
@@ -87,21 +93,26 @@ hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float 
                       hipStream_t s)
 {
     if (!m->geo32) return fail(HB_ERR_INVALID_ARG, "the FP32 operator needs a mesh built with HB_MESH_FP32");
+    const bool d = (m->desc.flags & HB_MESH_DIRICHLET) != 0;
     switch (m->N) {
-#define HB_CASE(n) \
-    case n: return launch_ax32_##n(m, lambda, x, y, partial, st, s);
+#define HB_CASE(n)                                                                \
+    case n:                                                                       \
+        return d ? launch_ax32_d_##n(m, lambda, x, y, partial, st, s)             \
+                 : launch_ax32_##n(m, lambda, x, y, partial, st, s);
         HB_ALL_N(HB_CASE)
 #undef HB_CASE
     default: return fail(HB_ERR_INVALID_ARG, "unsupported degree N");
     }
 }
 
-hb_status launch_batch_ax(int N, const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
-                          hipStream_t s)
+hb_status launch_batch_ax(int N, const void *D, bool fp32, bool dirichlet, const WorkItem *items, int nitems,
+                          const BatchProb *probs, hipStream_t s)
 {
     switch (N) {
-#define HB_CASE(n) \
-    case n: return launch_batch_ax_##n(D, fp32, items, nitems, probs, s);
+#define HB_CASE(n)                                                                \
+    case n:                                                                       \
+        return dirichlet ? launch_batch_ax_d_##n(D, fp32, items, nitems, probs, s) \
+                         : launch_batch_ax_##n(D, fp32, items, nitems, probs, s);
         HB_ALL_N(HB_CASE)
 #undef HB_CASE
     default: return fail(HB_ERR_INVALID_ARG, "unsupported degree N");

@@ -116,7 +116,7 @@ __device__ inline void atomic_add(gptr<T> p, T v)
 // Every thread of the block must call it (it synchronises the block).
 // (Always inlined: the single-problem and the batched kernel both call it, and
 // an out-of-line call would spill the whole register set.)
-template <int N, bool DOT, typename T, int V>
+template <int N, bool DOT, typename T, int V, bool MASK>
 __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
                                gptr<const T> __restrict__ geo, gptr<const T> __restrict__ Dm, T lambda,
                                gptr<const double> __restrict__ x, gptr<T> __restrict__ y,
@@ -169,11 +169,16 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
         else
             idx[c] = me[c * np2];
     }
+    if constexpr (MASK) {
 #pragma unroll
-    for (int c = 0; c < n1; ++c) {
-        const bool dof = idx[c] != kNoDof;
-        const double v = x[dof ? idx[c] : 0u];
-        q[c] = dof ? static_cast<T>(v) : T(0);
+        for (int c = 0; c < n1; ++c) {
+            const bool dof = idx[c] != kNoDof;
+            const double v = x[dof ? idx[c] : 0u];
+            q[c] = dof ? static_cast<T>(v) : T(0);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < n1; ++c) q[c] = static_cast<T>(x[idx[c]]);
     }
 
     // G is streamed once: non-temporal loads keep it from evicting x and y from
@@ -279,6 +284,13 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             yv[c] += s;
         }
     }
+    if constexpr (MASK) {
+        // materialise the outputs here: the assembly below is conditional per
+        // node, and the compiler would otherwise sink each output's last sums
+        // into its own branch and serialise them
+#pragma unroll
+        for (int c = 0; c < n1; ++c) pin(yv[c]);
+    }
     // assemble through Z^T.  Where several elements share a wave, the a = 0 face
     // node of an element is the a = N face node of the previous one whenever the
     // two are neighbours along r: the lanes holding them then see the same index,
@@ -301,13 +313,18 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             const T v_next = __shfl(yv[c], lane + kShift);
             const bool recv = may_recv && id_next == id;
             const bool sent = may_send && id_prev == id;
-            if (active && !sent && id != static_cast<int>(kNoDof))
+            if (active && !sent && (!MASK || id != static_cast<int>(kNoDof)))
                 atomic_add(&y[idx[c]], recv ? yv[c] + v_next : yv[c]);
         }
     } else if (active) {
+        if constexpr (MASK) {
 #pragma unroll
-        for (int c = 0; c < n1; ++c)
-            if (idx[c] != kNoDof) atomic_add(&y[idx[c]], yv[c]);
+            for (int c = 0; c < n1; ++c)
+                if (idx[c] != kNoDof) atomic_add(&y[idx[c]], yv[c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < n1; ++c) atomic_add(&y[idx[c]], yv[c]);
+        }
     }
     if constexpr (DOT) {
         // sum_e x_e . y_e = x . Z^T y_L = x . A x, accumulated in FP64
@@ -321,7 +338,7 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
     }
 }
 
-template <int N, bool DOT, typename T, int V>
+template <int N, bool DOT, typename T, int V, bool MASK>
 __global__ __launch_bounds__((AxShape<N, V>::threads))
 __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
     int64_t E, TileWalk walk, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm,
@@ -332,7 +349,7 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
         // stopped, or stopping at the next alpha step (which reads no partials)
         if (st->done | st->pending) return;
     }
-    ax_tile<N, DOT, T, V>(E, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), to_global(map), to_global(geo), to_global(Dm),
+    ax_tile<N, DOT, T, V, MASK>(E, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), to_global(map), to_global(geo), to_global(Dm),
                           lambda, to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));
 }
 
@@ -361,7 +378,7 @@ __device__ inline double uniform(double v)
 // list, with p.Ap fused.  D depends only on the degree, so all problems of a
 // class share it; as a read-only kernel argument its block-uniform entries come
 // through scalar loads.
-template <int N, typename T, int V>
+template <int N, typename T, int V, bool MASK>
 __global__ __launch_bounds__((AxShape<N, V>::threads))
 __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void batch_ax_kernel(const WorkItem *__restrict__ items,
                                                                          const BatchProb *__restrict__ probs,
@@ -378,10 +395,10 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void batch_ax_ker
     const auto x = to_global(uniform(P.p));
     const auto part = to_global(uniform(P.part_ax) + tile);
     if constexpr (sizeof(T) == 4)
-        ax_tile<N, true, float, V>(E, tile, map, to_global(uniform(P.geo32)), to_global(Dm),
+        ax_tile<N, true, float, V, MASK>(E, tile, map, to_global(uniform(P.geo32)), to_global(Dm),
                                    static_cast<float>(uniform(P.lambda)), x, to_global(uniform(P.Ap32)), part);
     else
-        ax_tile<N, true, double, V>(E, tile, map, to_global(uniform(P.geo)), to_global(Dm), uniform(P.lambda), x,
+        ax_tile<N, true, double, V, MASK>(E, tile, map, to_global(uniform(P.geo)), to_global(Dm), uniform(P.lambda), x,
                                     to_global(uniform(P.Ap)), part);
 }
 
@@ -424,7 +441,7 @@ int ax_epb_sched(int v)
     return with_schedule<N>(v, [&](auto VV) { return AxShape<N, decltype(VV)::value>::epb; });
 }
 
-template <int N, typename T>
+template <int N, typename T, bool MASK>
 hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambda, const double *x, T *y,
                       double *partial, CgState *st, hipStream_t s)
 {
@@ -435,17 +452,17 @@ hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambd
         const T lam = static_cast<T>(lambda);
         const TileWalk walk = make_walk(m->desc.nx, m->desc.ny, m->desc.nz, AxShape<N, V>::epb);
         if (st)
-            ax_kernel<N, true, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
+            ax_kernel<N, true, T, V, MASK><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
                                                                              y, partial, st);
         else
-            ax_kernel<N, false, T, V><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
+            ax_kernel<N, false, T, V, MASK><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
                                                                               y, nullptr, nullptr);
         HB_HIP(hipGetLastError());
         return HB_OK;
     });
 }
 
-template <int N>
+template <int N, bool MASK>
 hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
                             hipStream_t s)
 {
@@ -453,10 +470,10 @@ hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int
     return with_schedule<N>(ax_schedule(N, fp32), [&](auto VV) -> hb_status {
         constexpr int V = decltype(VV)::value;
         if (fp32)
-            batch_ax_kernel<N, float, V><<<nitems, AxShape<N, V>::threads, 0, s>>>(items, probs,
+            batch_ax_kernel<N, float, V, MASK><<<nitems, AxShape<N, V>::threads, 0, s>>>(items, probs,
                                                                                   static_cast<const float *>(D));
         else
-            batch_ax_kernel<N, double, V><<<nitems, AxShape<N, V>::threads, 0, s>>>(items, probs,
+            batch_ax_kernel<N, double, V, MASK><<<nitems, AxShape<N, V>::threads, 0, s>>>(items, probs,
                                                                                    static_cast<const double *>(D));
         HB_HIP(hipGetLastError());
         return HB_OK;
@@ -473,18 +490,39 @@ hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int
     hb_status launch_ax_##n(const hb_mesh_s *m, double l, const double *x, double *y, double *p, CgState *st,  \
                             hipStream_t s)                                                                     \
     {                                                                                                          \
-        return launch_ax_n<n, double>(m, m->geo, m->D, l, x, y, p, st, s);                                     \
+        return launch_ax_n<n, double, false>(m, m->geo, m->D, l, x, y, p, st, s);                              \
     }                                                                                                          \
     hb_status launch_ax32_##n(const hb_mesh_s *m, double l, const double *x, float *y, double *p, CgState *st, \
                               hipStream_t s)                                                                   \
     {                                                                                                          \
-        return launch_ax_n<n, float>(m, m->geo32, m->D32, l, x, y, p, st, s);                                  \
+        return launch_ax_n<n, float, false>(m, m->geo32, m->D32, l, x, y, p, st, s);                           \
     }                                                                                                          \
     hb_status launch_batch_ax_##n(const void *D, bool fp32, const WorkItem *it, int ni, const BatchProb *pr,   \
                                   hipStream_t s)                                                               \
     {                                                                                                          \
-        return launch_batch_ax_n<n>(D, fp32, it, ni, pr, s);                                                   \
+        return launch_batch_ax_n<n, false>(D, fp32, it, ni, pr, s);                                            \
     }                                                                                                          \
     int ax_grid_##n(int64_t E, int v) { return ax_grid_sched<n>(E, v); }                                       \
     int ax_epb_##n(int v) { return ax_epb_sched<n>(v); }                                                       \
+    }
+
+// The same entry points for Dirichlet boxes (boundary nodes without DOFs:
+// guarded gather and assembly), in translation units of their own.
+#define HB_AX_INSTANCE_DIRICHLET(n)                                                                            \
+    namespace hb {                                                                                             \
+    hb_status launch_ax_d_##n(const hb_mesh_s *m, double l, const double *x, double *y, double *p, CgState *st,\
+                              hipStream_t s)                                                                   \
+    {                                                                                                          \
+        return launch_ax_n<n, double, true>(m, m->geo, m->D, l, x, y, p, st, s);                               \
+    }                                                                                                          \
+    hb_status launch_ax32_d_##n(const hb_mesh_s *m, double l, const double *x, float *y, double *p,            \
+                                CgState *st, hipStream_t s)                                                    \
+    {                                                                                                          \
+        return launch_ax_n<n, float, true>(m, m->geo32, m->D32, l, x, y, p, st, s);                            \
+    }                                                                                                          \
+    hb_status launch_batch_ax_d_##n(const void *D, bool fp32, const WorkItem *it, int ni, const BatchProb *pr, \
+                                    hipStream_t s)                                                             \
+    {                                                                                                          \
+        return launch_batch_ax_n<n, true>(D, fp32, it, ni, pr, s);                                             \
+    }                                                                                                          \
     }

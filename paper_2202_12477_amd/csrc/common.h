@@ -84,6 +84,7 @@ struct BatchProb {
     int64_t E, NG;
     int32_t N, ax_tiles, vec_chunks, use32;  // use32: the operator of this problem is the FP32 one
     int32_t nx, ny, nz;                      // the box (host side: the order of the operator tiles)
+    int32_t dirichlet;                       // a Dirichlet box (host side: its class of operator launches)
 };
 
 // A unit of batched work: problem index and tile (operator) or chunk (vectors).
@@ -211,9 +212,10 @@ hb_status launch_round_f32(const double *in, float *out, int64_t n, hipStream_t 
 
 // Batched kernels (batch.hip).  Vector chunks hold kBatchChunk entries.
 constexpr int kBatchChunk = 4096;
-// D: the degree's derivative matrix (FP32 copy when fp32), shared by the class.
-hb_status launch_batch_ax(int N, const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
-                          hipStream_t s);
+// D: the degree's derivative matrix (FP32 copy when fp32), shared by the class;
+// dirichlet: the class's problems are Dirichlet boxes.
+hb_status launch_batch_ax(int N, const void *D, bool fp32, bool dirichlet, const WorkItem *items, int nitems,
+                          const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_alpha(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_residual(const WorkItem *items, int nitems, const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_beta(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s);

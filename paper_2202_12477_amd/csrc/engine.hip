@@ -126,6 +126,7 @@ class BatchRunner {
         P.nx = m->desc.nx;
         P.ny = m->desc.ny;
         P.nz = m->desc.nz;
+        P.dirichlet = (m->desc.flags & HB_MESH_DIRICHLET) ? 1 : 0;
         P.ax_tiles = ax_blocks(m, mixed);  // recomputed with the lists (schedule, precision)
         P.vec_chunks = static_cast<int32_t>((m->NG + kBatchChunk - 1) / kBatchChunk);
         P.use32 = mixed ? 1 : 0;
@@ -186,7 +187,7 @@ class BatchRunner {
     };
     struct Class {
         int N;
-        bool fp32;
+        bool fp32, dirichlet;
         int off;
         const void *D;              // the class's derivative matrix (any of its meshes)
         std::vector<Level> levels;  // items of the class's problems, by multiplier (descending)
@@ -201,7 +202,8 @@ class BatchRunner {
             const int need = static_cast<int>(j / iters) + 1;  // multiplier a problem needs to run sub-iteration j
             for (const Class &c : classes_) {
                 const int n = count_at(c.levels, need);
-                if (n > 0 && (st = launch_batch_ax(c.N, c.D, c.fp32, items_ + c.off, n, probs_, s))) return st;
+                if (n > 0 && (st = launch_batch_ax(c.N, c.D, c.fp32, c.dirichlet, items_ + c.off, n, probs_, s)))
+                    return st;
             }
             const int nrun = count_at(run_levels_, need), nvec = count_at(vec_levels_, need);
             if ((st = launch_batch_alpha(plist_, nrun, probs_, s)) ||
@@ -349,11 +351,12 @@ class BatchRunner {
         classes_.clear();
         int nit = 0;
         for (int N = 1; N <= kMaxN; ++N)
-            for (int f = 0; f < 2; ++f) {
-                Class c{N, f != 0, nit, nullptr, {}};
+            for (int k = 0; k < 4; ++k) {
+                const int f = k & 1, dir = k >> 1;
+                Class c{N, f != 0, dir != 0, nit, nullptr, {}};
                 for (int i : run) {
                     const BatchProb &P = h_probs_[i];
-                    if (P.N != N || P.use32 != f) continue;
+                    if (P.N != N || P.use32 != f || P.dirichlet != dir) continue;
                     c.D = f ? static_cast<const void *>(P.D32) : static_cast<const void *>(P.D);
                     // the single-problem launch's tile order (locality of the shared lines)
                     const TileWalk w = ax_walk_for(P.N, P.nx, P.ny, P.nz, ax_schedule(P.N, f != 0));
