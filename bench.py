@@ -91,6 +91,42 @@ def cpu_baseline(case, reps=60):
                       f"({m.NG} DOFs), one thread, {dt:.1f} s"}
 
 
+def paper_workload(hb, torch, metrics, B, n=50, N=7):
+    """The paper's own single-GPU workload at N=7, for comparison with its figures
+    (context, other hardware): a Dirichlet box of n^3 affine elements, (nN-1)^3 DOFs
+    (42,508,549 at n=50), 50 back-to-back operator applications and 100 CG
+    iterations, both FP64."""
+    m = hb.Mesh(n, n, n, N, dirichlet=True)
+    b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+    hb.rhs_uniform(b, 3)
+    y = torch.zeros_like(b)
+    x = torch.empty_like(b)
+    m.ax_add(1.0, b, y)
+    m.cg(1.0, b, x, max_iter=10, fixed_iters=True, history=False)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(AX_CALLS):
+        m.ax_add(1.0, b, y)
+    ev[1].record()
+    res = m.cg(1.0, b, x, max_iter=CG_ITERS, fixed_iters=True, history=False)
+    ev[2].record()
+    ev[2].synchronize()
+    assert res.iters == CG_ITERS and res.status == hb.HB_OK, res
+    t_ax = ev[0].elapsed_time(ev[1]) * 1e-3 / AX_CALLS
+    t_cg = ev[1].elapsed_time(ev[2]) * 1e-3
+    gflops = metrics.ax_flops(m.E, N) / t_ax / 1e9
+    out = {"workload": f"Dirichlet box {n}^3, N={N}, {m.NG} DOFs, affine, lambda=1",
+           "ax_us": round(t_ax * 1e6, 1), "ax_gdofs": round(m.NG / t_ax / 1e9, 2), "ax_gflops": round(gflops, 1),
+           "ax_frac_of_stream": round(metrics.ax_bytes_fused(m.NG, m.NL) / t_ax / 1e9 / B, 4),
+           "ax_frac_of_paper_roofline": round(gflops / metrics.op_roofline(N, B), 4),
+           "cg_gdofs": round(metrics.throughput(m.NG, CG_ITERS, 1, t_cg) / 1e9, 2),
+           "cg_fom_gflops_nekbone": round(metrics.fom(m.E, N, CG_ITERS, t_cg) / 1e9, 1),
+           "paper_mi250x_gcd_context": {"ax_gflops_n7": 1628.3, "cg_fom_gflops_n7_42.5M": 896.5,
+                                        "cg_gdofs_n7_42.5M": 4.58}}
+    m.close()
+    return out
+
+
 def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
     """The 64 uneven problems: one-by-one FP64 CG vs the batched solver (FP64, and
     FP32 operator with FP64 residual replacement with plain launches and with
@@ -248,6 +284,7 @@ def main():
     }
     m.close()
     del b, y, yk, x
+    out["paper_workload"] = paper_workload(hb, torch, metrics, B)
     if not args.no_batch:
         out["batch"] = batched_vs_sequential(hb, torch, inputs)
     if args.serve_requests > 0:
