@@ -59,6 +59,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_geometry.argtypes = [i32, i32, i32, i32, dp, i32, dp]
         L.oracle_ax.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp]
         L.oracle_ax.restype = None
+        L.oracle_diag.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp]
+        L.oracle_diag.restype = None
+        L.oracle_pcg.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp, dp, i32, i32, f64, i32, dp,
+                                 ctypes.POINTER(ctypes.c_int)]
         L.oracle_cg.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp, i32, i32, f64, i32, dp, dp, dp, dp,
                                 ctypes.POINTER(ctypes.c_int)]
         _lib = L
@@ -163,6 +167,28 @@ class Mesh:
                              _p(pap), ctypes.byref(it))
         j = it.value
         return dict(x=x, iters=j, status=st, res=res[: j + 1], alpha=al[:j], beta=be[:j], pap=pap[:j])
+
+    def diag(self, lam: float) -> np.ndarray:
+        """Diagonal of the assembled operator (the Jacobi preconditioner's M)."""
+        d = np.empty(self.NG)
+        lib().oracle_diag(self.E, self.N, _p(self.D), _p(self.geo), _p(self.map, ctypes.c_int64), self.NG, lam,
+                          _p(d))
+        return d
+
+    def pcg(self, b: np.ndarray, lam: float, x0: np.ndarray | None = None, *, fixed_iters: int = 0,
+            max_iter: int = 1000, rtol: float = 1e-8, compensated: bool = True, inv: np.ndarray | None = None):
+        """Algorithm 1 with the Jacobi preconditioner (inv: M^{-1} as a vector, default
+        1/diag(A)).  Returns dict(x, iters, status, res)."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(self.NG) if x0 is None else np.array(x0, dtype=np.float64)
+        inv = 1.0 / self.diag(lam) if inv is None else np.ascontiguousarray(inv, dtype=np.float64)
+        res = np.zeros(max(fixed_iters, max_iter) + 1)
+        it = ctypes.c_int(0)
+        st = lib().oracle_pcg(self.E, self.N, _p(self.D), _p(self.geo), _p(self.map, ctypes.c_int64), self.NG, lam,
+                              _p(inv), _p(b), _p(x), max_iter, fixed_iters, rtol, int(compensated), _p(res),
+                              ctypes.byref(it))
+        j = it.value
+        return dict(x=x, iters=j, status=st, res=res[: j + 1])
 
     def geo_view(self) -> np.ndarray:
         """Geometric factors as [E, 7, Np] (rr, rs, rt, ss, st, tt, c)."""

@@ -397,6 +397,45 @@ void oracle_ax(int64_t E, int N, const double *D, const double *geo, const int64
     free(q); free(qr); free(qs); free(qt); free(fr); free(fs); free(ft); free(ye);
 }
 
+/* The diagonal of the assembled operator, for the Jacobi preconditioner (a
+ * NekBone option the paper leaves out): diag(A)_g = sum over the local nodes i
+ * of g of (D^T G D + lambda C)_ii, with, at node i = (a,b,c),
+ *   (D^T G D)_ii = sum_m D[m][a]^2 G_rr(m,b,c) + sum_m D[m][b]^2 G_ss(a,m,c)
+ *                + sum_m D[m][c]^2 G_tt(a,b,m)
+ *                + 2 D[a][a] D[b][b] G_rs(i) + 2 D[a][a] D[c][c] G_rt(i)
+ *                + 2 D[b][b] D[c][c] G_st(i)
+ * (the r-derivative of q at node n depends on q_i only when n shares b and c
+ * with i, so the cross terms meet only at n = i). */
+void oracle_diag(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+                 double lambda, double *diag)
+{
+    int n1 = N + 1;
+    int64_t Np = (int64_t)n1 * n1 * n1;
+#define IDX(a, b, c) ((a) + n1 * ((b) + n1 * (c)))
+    for (int64_t g = 0; g < NG; ++g) diag[g] = 0.0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int64_t *me = map + e * Np;
+        const double *ge = geo + e * 7 * Np;
+        for (int c = 0; c <= N; ++c)
+            for (int b = 0; b <= N; ++b)
+                for (int a = 0; a <= N; ++a) {
+                    int64_t i = IDX(a, b, c);
+                    if (me[i] < 0) continue;
+                    double s = 0.0;
+                    for (int m = 0; m <= N; ++m) {
+                        s += D[m * n1 + a] * D[m * n1 + a] * ge[0 * Np + IDX(m, b, c)];
+                        s += D[m * n1 + b] * D[m * n1 + b] * ge[3 * Np + IDX(a, m, c)];
+                        s += D[m * n1 + c] * D[m * n1 + c] * ge[5 * Np + IDX(a, b, m)];
+                    }
+                    double Daa = D[a * n1 + a], Dbb = D[b * n1 + b], Dcc = D[c * n1 + c];
+                    s += 2.0 * Daa * Dbb * ge[1 * Np + i] + 2.0 * Daa * Dcc * ge[2 * Np + i] +
+                         2.0 * Dbb * Dcc * ge[4 * Np + i];
+                    diag[me[i]] += s + lambda * ge[6 * Np + i];
+                }
+    }
+#undef IDX
+}
+
 /* ------------------------------------------------------------------------ */
 /* Conjugate gradient, Algorithm 1.                                          */
 /* ------------------------------------------------------------------------ */
@@ -470,5 +509,57 @@ int oracle_cg(int64_t E, int N, const double *D, const double *geo, const int64_
     if (fixed_iters > 0 && status == 1 && j == limit) status = 0;
     if (iters) *iters = j;
     free(r); free(p); free(Ap);
+    return status;
+}
+
+/*
+ * Algorithm 1 with the Jacobi preconditioner M = diag(A) (inv = 1/diag(A)):
+ * z = M^{-1} r takes the place of r in the direction update and in rho,
+ *   r_0 = b - A x, z_0 = M^{-1} r_0, p = z_0, rho_0 = r_0.z_0; each iteration:
+ *   Ap = A p; alpha = rho_j / p.Ap; x += alpha p; r -= alpha Ap;
+ *   z = M^{-1} r; rho_{j+1} = r.z; beta = rho_{j+1} / rho_j; p = z + beta p.
+ * res[j] = ||r_j|| (the unpreconditioned residual, also the stopping test);
+ * stopping, histories and return values as oracle_cg.
+ */
+int oracle_pcg(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+               double lambda, const double *inv, const double *b, double *x, int max_iter, int fixed_iters,
+               double rtol, int compensated, double *res, int *iters)
+{
+    double *r = malloc(sizeof(double) * NG), *z = malloc(sizeof(double) * NG), *p = malloc(sizeof(double) * NG),
+           *Ap = malloc(sizeof(double) * NG);
+    oracle_ax(E, N, D, geo, map, NG, lambda, x, Ap);
+    for (int64_t g = 0; g < NG; ++g) {
+        r[g] = b[g] - Ap[g];
+        z[g] = inv[g] * r[g];
+        p[g] = z[g];
+    }
+    double rho = dot(NG, r, z, compensated);
+    double rr = dot(NG, r, r, compensated);
+    double bnorm = sqrt(dot(NG, b, b, compensated));
+    if (res) res[0] = sqrt(rr);
+    int limit = fixed_iters > 0 ? fixed_iters : max_iter;
+    int status = 1, j = 0;
+    if (fixed_iters <= 0 && sqrt(rr) <= rtol * bnorm) status = 0;
+    while (status == 1 && j < limit) {
+        if (rho == 0.0) { status = 0; break; }
+        oracle_ax(E, N, D, geo, map, NG, lambda, p, Ap);
+        double pAp = dot(NG, p, Ap, compensated);
+        if (!(pAp > 0.0)) { status = 2; break; }
+        double alpha = rho / pAp;
+        for (int64_t g = 0; g < NG; ++g) x[g] = x[g] + alpha * p[g];
+        for (int64_t g = 0; g < NG; ++g) r[g] = r[g] - alpha * Ap[g];
+        for (int64_t g = 0; g < NG; ++g) z[g] = inv[g] * r[g];
+        double rho_new = dot(NG, r, z, compensated);
+        rr = dot(NG, r, r, compensated);
+        double beta = rho_new / rho;
+        for (int64_t g = 0; g < NG; ++g) p[g] = z[g] + beta * p[g];
+        rho = rho_new;
+        ++j;
+        if (res) res[j] = sqrt(rr);
+        if (fixed_iters <= 0 && sqrt(rr) <= rtol * bnorm) status = 0;
+    }
+    if (fixed_iters > 0 && status == 1 && j == limit) status = 0;
+    if (iters) *iters = j;
+    free(r); free(z); free(p); free(Ap);
     return status;
 }
