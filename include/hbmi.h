@@ -71,6 +71,15 @@ typedef enum {
     HB_PREC_FP32_RR = 2   /* one CG with the FP32 operator and FP64 residual replacement */
 } hb_prec;                /* both mixed modes need HB_MESH_FP32 */
 
+/* Preconditioner of hb_cg_solve.  The paper's benchmark runs CG without one;
+ * NekBone (whose benchmark hipBone re-implements) offers the Jacobi option. */
+typedef enum {
+    HB_PRECOND_NONE = 0,
+    HB_PRECOND_JACOBI = 1 /* M = diag(A) (computed on the device per mesh and lambda, 8 N_G bytes kept with the
+                             mesh's CG workspace): z = M^{-1} r replaces r in rho = r.z and p = z + beta p; the
+                             residual history and the stop test stay on ||r|| */
+} hb_precond;
+
 typedef struct hb_mesh_s *hb_mesh;
 
 /* Box mesh on [0,1]^3 (NekBone section: a regular mesh of E hexahedra with
@@ -170,6 +179,8 @@ typedef struct {
                             hb_batch_solve: > 0 makes each segment graph_k iterations long (instead of
                             check_every) and replays it from a captured graph until the set of running
                             problems changes. At most 4096. */
+    int32_t precond;     /* hb_precond; HB_PRECOND_JACOBI with HB_PREC_FP64 in hb_cg_solve only (hb_batch_solve
+                            and the engine take HB_PRECOND_NONE) */
 } hb_cg_opts;
 
 typedef struct {

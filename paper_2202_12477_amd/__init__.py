@@ -32,6 +32,8 @@ MESH_DIRICHLET = 2
 PREC_FP64 = 0
 PREC_FP32_IR = 1
 PREC_FP32_RR = 2
+PRECOND_NONE = 0
+PRECOND_JACOBI = 1
 
 # Every entry point of include/hbmi.h, in declaration order.
 EXPORTS = (
@@ -73,7 +75,8 @@ class _EngineInfo(ctypes.Structure):
 class _CgOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("graph_k", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("graph_k", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
 
 class _CgResult(ctypes.Structure):
@@ -261,17 +264,18 @@ class Mesh:
 
     def cg(self, lam: float, b, x, *, max_iter: int = 100, fixed_iters: bool = True, rtol: float = 0.0,
            x0_zero: bool = True, check_every: int = 0, history: bool = True, prec: int = PREC_FP64,
-           max_outer: int = 0, inner_rtol: float = 0.0, graph_k: int = 0, stream=None,
-           raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)) -> CgResult:
+           max_outer: int = 0, inner_rtol: float = 0.0, graph_k: int = 0, precond: int = PRECOND_NONE,
+           stream=None, raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)) -> CgResult:
         """Algorithm 1 on the device (prec=PREC_FP64), or FP64 refinement around the FP32-operator CG
         (prec=PREC_FP32_IR / PREC_FP32_RR); x holds the initial guess (unless x0_zero) and the result.
-        graph_k > 0 replays a captured graph of graph_k iterations instead of launching each kernel."""
+        graph_k > 0 replays a captured graph of graph_k iterations instead of launching each kernel;
+        precond=PRECOND_JACOBI (FP64 only) preconditions with the assembled diagonal of A."""
         import torch
 
         if b.numel() != self.NG or x.numel() != self.NG:
             raise ValueError("vectors must have N_G entries")
         opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, max_outer, inner_rtol,
-                       graph_k)
+                       graph_k, precond)
         res = _CgResult()
         hist = (ctypes.c_double * (max_iter + 1))() if history else None
         st = lib().hb_cg_solve(self.handle, lam, _ptr(b, torch.float64), _ptr(x, torch.float64), ctypes.byref(opts),
@@ -287,7 +291,8 @@ class Mesh:
 
 def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool = False, rtol: float = 1e-8,
                 x0_zero: bool = True, check_every: int = 0, prec: int = PREC_FP64, inner_rtol: float = 0.0,
-                graph_k: int = 0, stream=None, raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
+                graph_k: int = 0, precond: int = PRECOND_NONE, stream=None,
+                raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
     """Solve independent problems together (hb_batch_solve); returns (status, [CgResult]).
     graph_k > 0: segments of graph_k iterations replayed from captured graphs."""
     import torch
@@ -303,7 +308,8 @@ def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool 
     B = (ctypes.c_void_p * n)(*[_ptr(b, torch.float64) for b in bs])
     X = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64) for x in xs])
     R = (_CgResult * n)()
-    opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, 0, inner_rtol, graph_k)
+    opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, 0, inner_rtol, graph_k,
+                   precond)
     st = lib().hb_batch_solve(n, H, L, B, X, ctypes.byref(opts), R, _stream(stream))
     if st in raise_on:
         _check(st, "hb_batch_solve")

@@ -244,6 +244,10 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
         return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: mixed precision needs a tolerance (fixed_iters = 0)");
     if (mixed && !m->geo32)
         return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: mixed precision needs a mesh built with HB_MESH_FP32");
+    if (opts->precond != HB_PRECOND_NONE && opts->precond != HB_PRECOND_JACOBI)
+        return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: unknown preconditioner");
+    if (opts->precond == HB_PRECOND_JACOBI && mixed)
+        return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: the Jacobi preconditioner is available with HB_PREC_FP64 only");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hb_status st = ensure_cg(m, opts->max_iter, mixed, opts->prec == HB_PREC_FP32_IR);
     if (st) return st;
@@ -251,21 +255,26 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
     w.graph_k = opts->graph_k;
     if (opts->prec == HB_PREC_FP32_RR) return solve_replace(m, lambda, dev_b, dev_x, opts, result, host_res_hist, s);
     if (!mixed) {
-        if ((st = run_cg<double>(m, lambda, dev_b, dev_x, w.Ap, opts->x0_zero, opts->max_iter,
-                                 opts->fixed_iters ? -1.0 : opts->rtol, opts->check_every, s)))
-            return st;
+        const bool pc = opts->precond == HB_PRECOND_JACOBI;
+        if (pc && (st = ensure_jacobi(m, lambda, s))) return st;
+        w.pc = pc;
+        st = run_cg<double>(m, lambda, dev_b, dev_x, w.Ap, opts->x0_zero, opts->max_iter,
+                            opts->fixed_iters ? -1.0 : opts->rtol, opts->check_every, s);
+        w.pc = false;
+        if (st) return st;
         const CgState hs = *w.host_state;
-        double rho0 = 0.0, rho_last = 0.0;
-        HB_HIP(hipMemcpy(&rho0, w.rho, sizeof(double), hipMemcpyDeviceToHost));
-        HB_HIP(hipMemcpy(&rho_last, w.rho + hs.iters, sizeof(double), hipMemcpyDeviceToHost));
+        // ||r_0|| and ||r_iters|| (hist holds the residual norms in both forms of the iteration)
+        double res0 = 0.0, res_last = 0.0;
+        HB_HIP(hipMemcpy(&res0, w.hist, sizeof(double), hipMemcpyDeviceToHost));
+        HB_HIP(hipMemcpy(&res_last, w.hist + hs.iters, sizeof(double), hipMemcpyDeviceToHost));
         if (host_res_hist)
             HB_HIP(hipMemcpy(host_res_hist, w.hist, sizeof(double) * (hs.iters + 1), hipMemcpyDeviceToHost));
         if (result) {
             *result = hb_cg_result{};
             result->iters = hs.iters;
             result->status = hs.status;
-            result->res0 = std::sqrt(rho0);
-            result->res = std::sqrt(rho_last);
+            result->res0 = res0;
+            result->res = res_last;
             result->bnorm = std::sqrt(hs.bb);
         }
         return static_cast<hb_status>(hs.status);

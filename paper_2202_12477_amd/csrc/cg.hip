@@ -47,19 +47,27 @@ __global__ void setup_state_kernel(CgState *st, int max_iter, double rtol)
 }
 
 // r0 = b - A x0 (Ap holds A x0 unless x0 = 0), p = r0, Ap = 0; partials of r0.r0 and b.b.
-template <typename TAp>
+// PC (Jacobi): p = z0 = inv r0, and a third partial array of r0.z0.
+template <typename TAp, bool PC>
 __global__ __launch_bounds__(kVecThreads) void init_kernel(int64_t n, const double *__restrict__ b,
                                                           double *__restrict__ x, double *__restrict__ r,
                                                           double *__restrict__ p, TAp *__restrict__ Ap,
-                                                          int x0_zero, double *__restrict__ partial)
+                                                          int x0_zero, const double *__restrict__ inv,
+                                                          double *__restrict__ partial)
 {
     __shared__ double red[kVecThreads / 64];
-    double rr = 0.0, bb = 0.0;
+    double rr = 0.0, bb = 0.0, rz = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double bi = b[i];
         const double ri = x0_zero ? bi : bi - static_cast<double>(Ap[i]);
         r[i] = ri;
-        p[i] = ri;
+        if constexpr (PC) {
+            const double zi = inv[i] * ri;
+            p[i] = zi;
+            rz += ri * zi;
+        } else {
+            p[i] = ri;
+        }
         Ap[i] = TAp(0);
         if (x0_zero) x[i] = 0.0;
         rr += ri * ri;
@@ -67,22 +75,25 @@ __global__ __launch_bounds__(kVecThreads) void init_kernel(int64_t n, const doub
     }
     rr = block_sum(rr, red);
     bb = block_sum(bb, red);
+    if constexpr (PC) rz = block_sum(rz, red);
     if (threadIdx.x == 0) {
         partial[blockIdx.x] = rr;
         partial[gridDim.x + blockIdx.x] = bb;
+        if constexpr (PC) partial[2 * gridDim.x + blockIdx.x] = rz;
     }
 }
 
 __global__ __launch_bounds__(kFinThreads) void init_finish_kernel(const double *__restrict__ partial, int nblk,
-                                                                 CgState *st, double *__restrict__ rho,
+                                                                 int pc, CgState *st, double *__restrict__ rho,
                                                                  double *__restrict__ hist)
 {
     __shared__ double red[kFinThreads / 64];
-    const double rho0 = sum_partials(partial, nblk, red);
+    const double rho0 = sum_partials(partial, nblk, red);  // r0.r0: the stop tests
     const double bb = sum_partials(partial + nblk, nblk, red);
+    const double rz0 = pc ? sum_partials(partial + 2 * nblk, nblk, red) : rho0;
     if (threadIdx.x != 0) return;
     st->bb = bb;
-    rho[0] = rho0;
+    rho[0] = rz0;
     hist[0] = sqrt(rho0);
     st->stop_res = st->rtol >= 0.0 ? st->rtol * sqrt(bb) : -1.0;
     if (!isfinite(rho0)) {
@@ -102,45 +113,100 @@ __global__ __launch_bounds__(kFinThreads) void alpha_kernel(const double *__rest
     alpha_step(partial, nblk, st, rho);
 }
 
-// r -= alpha Ap; partials of r.r.
-template <typename TAp>
+// r -= alpha Ap; partials of r.r (PC: of r.z, z = inv r, then of r.r).
+template <typename TAp, bool PC>
 __global__ __launch_bounds__(kVecThreads) void residual_kernel(int64_t n, double *__restrict__ r,
                                                               const TAp *__restrict__ Ap,
+                                                              const double *__restrict__ inv,
                                                               double *__restrict__ partial, const CgState *st)
 {
     if (st->done) return;
     __shared__ double red[kVecThreads / 64];
     const double alpha = st->alpha;
-    double rr = 0.0;
+    double rr = 0.0, rz = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double ri = r[i] - alpha * static_cast<double>(Ap[i]);
         r[i] = ri;
         rr += ri * ri;
+        if constexpr (PC) rz += ri * (inv[i] * ri);
     }
     rr = block_sum(rr, red);
-    if (threadIdx.x == 0) partial[blockIdx.x] = rr;
+    if constexpr (PC) {
+        rz = block_sum(rz, red);
+        if (threadIdx.x == 0) {
+            partial[blockIdx.x] = rz;
+            partial[gridDim.x + blockIdx.x] = rr;
+        }
+    } else {
+        if (threadIdx.x == 0) partial[blockIdx.x] = rr;
+    }
 }
 
-__global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restrict__ partial, int nblk, CgState *st,
-                                                          double *__restrict__ rho, double *__restrict__ hist)
+__global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restrict__ partial, int nblk, int pc,
+                                                          CgState *st, double *__restrict__ rho,
+                                                          double *__restrict__ hist)
 {
-    beta_step(partial, nblk, st, rho, hist);
+    beta_step(partial, nblk, st, rho, hist, pc != 0);
 }
 
-// x += alpha p; p = r + beta p; Ap = 0 (the next operator call assembles into it).
-template <typename TAp>
+// x += alpha p; p = r + beta p (PC: p = inv r + beta p); Ap = 0 (the next
+// operator call assembles into it).
+template <typename TAp, bool PC>
 __global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *__restrict__ x, double *__restrict__ p,
                                                             const double *__restrict__ r, TAp *__restrict__ Ap,
-                                                            const CgState *st)
+                                                            const double *__restrict__ inv, const CgState *st)
 {
     if (st->done) return;
     const double alpha = st->alpha, beta = st->beta;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double pi = p[i];
         x[i] += alpha * pi;
-        p[i] = r[i] + beta * pi;
+        if constexpr (PC)
+            p[i] = inv[i] * r[i] + beta * pi;
+        else
+            p[i] = r[i] + beta * pi;
         Ap[i] = TAp(0);
     }
+}
+
+// Diagonal of the assembled operator, one thread per local node: at node
+// (a,b,c) of an element, (D^T G D + lambda C)_ii = sum_m D[m][a]^2 G_rr(m,b,c)
+// + sum_m D[m][b]^2 G_ss(a,m,c) + sum_m D[m][c]^2 G_tt(a,b,m)
+// + 2 (D_aa D_bb G_rs + D_aa D_cc G_rt + D_bb D_cc G_st)(i) + lambda c(i),
+// assembled by atomic addition (the cross terms meet only at the node itself).
+__global__ __launch_bounds__(256) void jacobi_diag_kernel(int64_t nl, int N, const int32_t *__restrict__ map,
+                                                          const double *__restrict__ geo,
+                                                          const double *__restrict__ Dm, double lambda,
+                                                          double *__restrict__ diag)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nl) return;
+    const int32_t g = map[t];
+    if (g < 0) return;
+    const int n1 = N + 1;
+    const int64_t np2 = (int64_t)n1 * n1, np3 = np2 * n1;
+    const int64_t e = t / np3;
+    const int n = static_cast<int>(t - e * np3);
+    const int a = n % n1, b = (n / n1) % n1, c = n / (n1 * n1);
+    // layer-major geometry: factor f of node (a', b', c') at [(e np3 + c' np2) 7 + f np2 + a' + n1 b']
+    auto G = [&](int f, int aa, int bb, int cc) {
+        return geo[(e * np3 + cc * np2) * kGeo + f * np2 + aa + n1 * bb];
+    };
+    double s = 0.0;
+    for (int m = 0; m < n1; ++m) {
+        s += Dm[m * n1 + a] * Dm[m * n1 + a] * G(0, m, b, c);
+        s += Dm[m * n1 + b] * Dm[m * n1 + b] * G(3, a, m, c);
+        s += Dm[m * n1 + c] * Dm[m * n1 + c] * G(5, a, b, m);
+    }
+    const double Daa = Dm[a * n1 + a], Dbb = Dm[b * n1 + b], Dcc = Dm[c * n1 + c];
+    s += 2.0 * Daa * Dbb * G(1, a, b, c) + 2.0 * Daa * Dcc * G(2, a, b, c) + 2.0 * Dbb * Dcc * G(4, a, b, c);
+    atomicAdd(&diag[g], s + lambda * G(6, a, b, c));
+}
+
+__global__ __launch_bounds__(kVecThreads) void invert_kernel(int64_t n, double *__restrict__ v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = 1.0 / v[i];
 }
 
 // r = b - t; partials of r.r.
@@ -239,8 +305,11 @@ hb_status launch_cg_init(int64_t n, const double *b, double *x, double *r, doubl
                          CgWork &w, CgState *st, hipStream_t s)
 {
     const int g = vec_blocks(n);
-    init_kernel<TAp><<<g, kVecThreads, 0, s>>>(n, b, x, r, p, Ap, x0_zero, w.part_vec);
-    init_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, st, w.rho, w.hist);
+    if (w.pc)
+        init_kernel<TAp, true><<<g, kVecThreads, 0, s>>>(n, b, x, r, p, Ap, x0_zero, w.jinv, w.part_vec);
+    else
+        init_kernel<TAp, false><<<g, kVecThreads, 0, s>>>(n, b, x, r, p, Ap, x0_zero, nullptr, w.part_vec);
+    init_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, w.pc ? 1 : 0, st, w.rho, w.hist);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
@@ -255,22 +324,40 @@ hb_status launch_cg_alpha(CgWork &w, int ax_grid, CgState *st, hipStream_t s)
 template <typename TAp>
 hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, hipStream_t s)
 {
-    residual_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, w.part_vec, st);
+    if (w.pc)
+        residual_kernel<TAp, true><<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, w.jinv, w.part_vec, st);
+    else
+        residual_kernel<TAp, false><<<vec_blocks(n), kVecThreads, 0, s>>>(n, r, Ap, nullptr, w.part_vec, st);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
 hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, hipStream_t s)
 {
-    beta_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, vec_blocks(n), st, w.rho, w.hist);
+    beta_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, vec_blocks(n), w.pc ? 1 : 0, st, w.rho, w.hist);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
 template <typename TAp>
-hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, hipStream_t s)
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, const double *inv, CgState *st,
+                           hipStream_t s)
 {
-    update_kernel<TAp><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, st);
+    if (inv)
+        update_kernel<TAp, true><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, inv, st);
+    else
+        update_kernel<TAp, false><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, nullptr, st);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
+hb_status launch_jacobi_inverse(const hb_mesh_s *m, double lambda, double *inv, hipStream_t s)
+{
+    if (m->NG == 0) return HB_OK;
+    zero_kernel<double><<<vec_blocks(m->NG), kVecThreads, 0, s>>>(inv, m->NG);
+    jacobi_diag_kernel<<<static_cast<unsigned>((m->NL + 255) / 256), 256, 0, s>>>(m->NL, m->N, m->map, m->geo, m->D,
+                                                                                   lambda, inv);
+    invert_kernel<<<vec_blocks(m->NG), kVecThreads, 0, s>>>(m->NG, inv);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
@@ -281,10 +368,10 @@ template hb_status launch_cg_init<float>(int64_t, const double *, double *, doub
                                          CgWork &, CgState *, hipStream_t);
 template hb_status launch_cg_residual<double>(int64_t, double *, const double *, CgWork &, CgState *, hipStream_t);
 template hb_status launch_cg_residual<float>(int64_t, double *, const float *, CgWork &, CgState *, hipStream_t);
-template hb_status launch_cg_update<double>(int64_t, double *, double *, const double *, double *, CgState *,
-                                            hipStream_t);
-template hb_status launch_cg_update<float>(int64_t, double *, double *, const double *, float *, CgState *,
-                                           hipStream_t);
+template hb_status launch_cg_update<double>(int64_t, double *, double *, const double *, double *, const double *,
+                                            CgState *, hipStream_t);
+template hb_status launch_cg_update<float>(int64_t, double *, double *, const double *, float *, const double *,
+                                           CgState *, hipStream_t);
 
 hb_status launch_residual_norm(int64_t n, const double *b, const double *t, double *r, CgWork &w, double *out,
                                hipStream_t s)

@@ -55,24 +55,27 @@ __device__ inline void alpha_step(const double *__restrict__ partial, int nblk, 
     }
 }
 
-// rho_{j+1} = r.r, beta, history, convergence / iteration-cap test.
+// rho_{j+1} = r.r, beta, history, convergence / iteration-cap test.  With the
+// Jacobi preconditioner (pc) the partials hold r.z and then r.r: rho and beta
+// use r.z, the history and the stop test ||r||.
 __device__ inline void beta_step(const double *__restrict__ partial, int nblk, CgState *st, double *__restrict__ rho,
-                                 double *__restrict__ hist)
+                                 double *__restrict__ hist, bool pc = false)
 {
     __shared__ double red[kFinThreads / 64];
     if (st->done) return;
     const double rho_new = sum_partials(partial, nblk, red);
+    const double rr = pc ? sum_partials(partial + nblk, nblk, red) : rho_new;
     if (threadIdx.x != 0) return;
     const int j = st->it;
     st->beta = rho_new / rho[j];
     rho[j + 1] = rho_new;
-    hist[j + 1] = sqrt(rho_new);
+    hist[j + 1] = sqrt(rr);
     st->iters = j + 1;
     // this iteration's update still runs; the next alpha turns pending into done
-    if (!isfinite(rho_new)) {
+    if (!isfinite(rho_new) || !isfinite(rr)) {
         st->pending = 1;
         st->status = HB_ERR_BREAKDOWN;
-    } else if (rho_new == 0.0 || sqrt(rho_new) <= st->stop_res) {
+    } else if (rho_new == 0.0 || sqrt(rr) <= st->stop_res) {
         st->pending = 1;
         st->status = HB_OK;
     } else if (j + 1 >= st->max_iter) {

@@ -100,7 +100,7 @@ struct CgWork {
     double *part_ax = nullptr;  // operator block partials of p.Ap (>= operator grid)
     double *part_vec = nullptr; // vector-kernel block partials (>= 2 * vector grid)
     int32_t part_ax_len = 0, part_vec_len = 0;
-    double *rho = nullptr;      // r_j . r_j, j = 0..max_iter
+    double *rho = nullptr;      // r_j . r_j (r_j . z_j with the Jacobi preconditioner), j = 0..max_iter
     // mixed-precision refinement: outer residual, correction, FP32 operator output
     double *rout = nullptr, *d = nullptr;
     float *Ap32 = nullptr;
@@ -118,11 +118,17 @@ struct CgWork {
         int k = 0;
         double lambda = 0.0;
         const void *x = nullptr, *Ap = nullptr;
+        bool pc = false;  // Jacobi-preconditioned iteration
     };
     Graph graphs[2];
     int graph_next = 0;
     int graph_k = 0;           // the current solve's graph length (0: plain launches)
     hipStream_t cap = nullptr; // private stream the graphs are captured on
+    // Jacobi preconditioner: 1 / diag(A) for lambda = jlambda (allocated on first use)
+    double *jinv = nullptr;
+    double jlambda = 0.0;
+    bool jvalid = false;
+    bool pc = false;           // the current solve is preconditioned (iterations use jinv)
 };
 
 }  // namespace hb
@@ -196,7 +202,10 @@ template <typename TAp>
 hb_status launch_cg_residual(int64_t n, double *r, const TAp *Ap, CgWork &w, CgState *st, hipStream_t s);
 hb_status launch_cg_beta(int64_t n, CgWork &w, CgState *st, hipStream_t s);
 template <typename TAp>
-hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, CgState *st, hipStream_t s);
+hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, const double *inv, CgState *st,
+                          hipStream_t s);
+// 1 / diag(A) into inv (Jacobi preconditioner), for the mesh's operator at lambda.
+hb_status launch_jacobi_inverse(const hb_mesh_s *m, double lambda, double *inv, hipStream_t s);
 // Residual replacement after the completed iterations: r = b - t (t = A x
 // from the FP64 operator), rho_iters = r.r, history entry iters, *out = r.r;
 // then the solve resumes with a new stopping threshold on ||r||.

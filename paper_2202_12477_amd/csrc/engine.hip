@@ -544,6 +544,8 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
     if (!fixed && !(opts->rtol >= 0.0)) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: rtol must be >= 0");
     if (opts->graph_k < 0 || opts->graph_k > 4096)
         return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: graph_k must be in [0, 4096]");
+    if (opts->precond != HB_PRECOND_NONE)
+        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: no preconditioner is available here");
     for (int i = 0; i < nprob; ++i) {
         if (!meshes[i] || !dev_b[i] || !dev_x[i] || dev_b[i] == dev_x[i])
             return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": bad pointers");

@@ -13,6 +13,8 @@ void free_cg(hb_mesh_s *m);
 // Size the CG workspace of a mesh for an iteration cap (mixed: the FP32
 // operator output; refine: the buffers of the restarted refinement).
 hb_status ensure_cg(hb_mesh_s *m, int max_iter, bool mixed, bool refine = false);
+// 1 / diag(A) for the Jacobi preconditioner, computed for this lambda if needed.
+hb_status ensure_jacobi(hb_mesh_s *m, double lambda, hipStream_t s);
 hb_status read_state(CgWork &w, hipStream_t s);
 hb_status read_norm(CgWork &w, hipStream_t s, double *out);
 hb_status apply_op(const hb_mesh_s *m, double l, const double *x, double *y, double *part, CgState *st, hipStream_t s);

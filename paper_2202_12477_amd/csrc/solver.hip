@@ -21,7 +21,7 @@ static void drop_graphs(CgWork &w)
 void free_cg(hb_mesh_s *m)
 {
     CgWork &w = m->cg;
-    for (double *p : {w.r, w.p, w.Ap, w.part_ax, w.part_vec, w.rho, w.hist, w.rout, w.d, w.dnorm})
+    for (double *p : {w.r, w.p, w.Ap, w.part_ax, w.part_vec, w.rho, w.hist, w.rout, w.d, w.dnorm, w.jinv})
         if (p) (void)hipFree(p);
     if (w.Ap32) (void)hipFree(w.Ap32);
     if (w.state) (void)hipFree(w.state);
@@ -40,7 +40,8 @@ hb_status ensure_cg(hb_mesh_s *m, int max_iter, bool mixed, bool refine)
 {
     CgWork &w = m->cg;
     const int need_ax = ax_blocks_max(m);  // any schedule of either precision
-    const int need_vec = static_cast<int>(std::max<int64_t>(2 * vec_blocks(m->NG), (m->NG + kBatchChunk - 1) / kBatchChunk));
+    // three partial arrays for the first step of the preconditioned iteration
+    const int need_vec = static_cast<int>(std::max<int64_t>(3 * vec_blocks(m->NG), (m->NG + kBatchChunk - 1) / kBatchChunk));
     if (w.r && w.n == m->NG && w.hist_len >= max_iter + 1 && w.part_ax_len >= need_ax &&
         w.part_vec_len >= need_vec && (!mixed || w.Ap32) && (!refine || w.rout))
         return HB_OK;
@@ -108,7 +109,7 @@ static hb_status enqueue_iteration(hb_mesh_s *m, double lambda, double *x, TAp *
     if ((e = launch_cg_alpha(w, ax_blocks(m, sizeof(TAp) == 4), w.state, s))) return e;
     if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, s))) return e;
     if ((e = launch_cg_beta(n, w, w.state, s))) return e;
-    return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.state, s);
+    return launch_cg_update<TAp>(n, x, w.p, w.r, Ap, w.pc ? w.jinv : nullptr, w.state, s);
 }
 
 // k iterations as one executable graph: the cached one with the same
@@ -120,7 +121,7 @@ static hb_status iteration_graph(hb_mesh_s *m, double lambda, double *x, TAp *Ap
     CgWork &w = m->cg;
     for (const CgWork::Graph &g : w.graphs) {
         if (g.exec && g.elem == static_cast<int>(sizeof(TAp)) && g.k == k && g.lambda == lambda && g.x == x &&
-            g.Ap == Ap && g.epoch == ax_schedule_epoch()) {
+            g.Ap == Ap && g.epoch == ax_schedule_epoch() && g.pc == w.pc) {
             *out = g.exec;
             return HB_OK;
         }
@@ -152,6 +153,7 @@ static hb_status iteration_graph(hb_mesh_s *m, double lambda, double *x, TAp *Ap
     g.lambda = lambda;
     g.x = x;
     g.Ap = Ap;
+    g.pc = w.pc;
     *out = g.exec;
     return HB_OK;
 }
@@ -204,6 +206,27 @@ hb_status run_cg(hb_mesh_s *m, double lambda, const double *b, double *x, TAp *A
     }
     if ((st = launch_cg_init<TAp>(n, b, x, w.r, w.p, Ap, x0_zero, w, w.state, s))) return st;
     return cg_iterate<TAp>(m, lambda, x, Ap, max_iter, rtol < 0.0, check_every, s);
+}
+
+// The Jacobi preconditioner's 1 / diag(A) for this lambda (the workspace must
+// be sized; computed again only when lambda changes).
+hb_status ensure_jacobi(hb_mesh_s *m, double lambda, hipStream_t s)
+{
+    CgWork &w = m->cg;
+    if (!w.jinv) {
+        size_t tally = 0;
+        hb_status st = dev_alloc(&w.jinv, m->NG, &tally);
+        if (st) return st;
+        w.bytes += tally;
+        m->device_bytes += tally;
+        w.jvalid = false;
+    }
+    if (w.jvalid && w.jlambda == lambda) return HB_OK;
+    hb_status st = launch_jacobi_inverse(m, lambda, w.jinv, s);
+    if (st) return st;
+    w.jlambda = lambda;
+    w.jvalid = true;
+    return HB_OK;
 }
 
 // ||b - A x||^2 with the FP64 operator (t = A x in w.Ap, r = b - t in w.rout).
