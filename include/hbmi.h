@@ -59,9 +59,16 @@ typedef enum { HB_MASS_GWJ = 0, HB_MASS_INVDEG = 1 } hb_mass;
 /* Mesh flags. */
 enum {
     HB_MESH_FP32 = 1,     /* also keep FP32 geometric factors and D, for hb_ax_f32 and FP32 refinement */
-    HB_MESH_DIRICHLET = 2 /* homogeneous Dirichlet box (the paper's experiments): the nodes on the boundary of
+    HB_MESH_DIRICHLET = 2, /* homogeneous Dirichlet box (the paper's experiments): the nodes on the boundary of
                              [0,1]^3 carry no DOF, so N_G = (nx N - 1)(ny N - 1)(nz N - 1), numbered
                              lexicographically over the interior nodes; needs nx N, ny N, nz N >= 2 */
+    HB_MESH_GATHER = 4    /* two-phase operator (the Poisson Operator section's own form): the element kernel
+                             writes the local vector y_L (8 N_L bytes kept with the mesh), then a gather sums
+                             each DOF's local copies in ascending local order (Z^T as CSR rows, 4 (N_G + 1)
+                             + 4 N_L bytes, built at creation from the map on the host).  Every hb_ax, hb_ax_add
+                             and FP64 hb_cg_solve on the mesh uses it; its results are bit-identical from run
+                             to run.  FP64 only: not with HB_MESH_FP32; not accepted by hb_batch_solve or the
+                             engine; needs fewer than 2^32 local nodes */
 };
 
 /* Precision of hb_cg_solve. */

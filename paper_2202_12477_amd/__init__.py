@@ -29,6 +29,7 @@ MASS_GWJ = 0
 MASS_INVDEG = 1
 MESH_FP32 = 1
 MESH_DIRICHLET = 2
+MESH_GATHER = 4
 PREC_FP64 = 0
 PREC_FP32_IR = 1
 PREC_FP32_RR = 2
@@ -187,16 +188,18 @@ class Mesh:
     """A device-resident box mesh (hb_mesh_create / hb_mesh_destroy)."""
 
     def __init__(self, nx: int, ny: int, nz: int, N: int, jitter: float = 0.0, seed: int = 0,
-                 mass: int = MASS_GWJ, fp32: bool = False, dirichlet: bool = False, stream=None):
-        """dirichlet: the boundary nodes of the box carry no DOF (N_G = (nx N - 1)(ny N - 1)(nz N - 1))."""
-        flags = (MESH_FP32 if fp32 else 0) | (MESH_DIRICHLET if dirichlet else 0)
+                 mass: int = MASS_GWJ, fp32: bool = False, dirichlet: bool = False, gather: bool = False,
+                 stream=None):
+        """dirichlet: the boundary nodes of the box carry no DOF (N_G = (nx N - 1)(ny N - 1)(nz N - 1));
+        gather: the two-phase operator (local output, then a deterministic gather) for every FP64 call."""
+        flags = (MESH_FP32 if fp32 else 0) | (MESH_DIRICHLET if dirichlet else 0) | (MESH_GATHER if gather else 0)
         d = _MeshDesc(nx, ny, nz, N, jitter, seed, mass, flags)
         h = ctypes.c_void_p()
         _check(lib().hb_mesh_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)), "hb_mesh_create")
         self._h = h
         info = _MeshInfo()
         _check(lib().hb_mesh_query(h, ctypes.byref(info)), "hb_mesh_query")
-        self.nx, self.ny, self.nz, self.N, self.dirichlet = nx, ny, nz, N, dirichlet
+        self.nx, self.ny, self.nz, self.N, self.dirichlet, self.gather = nx, ny, nz, N, dirichlet, gather
         self.E, self.NL, self.NG = info.n_elem, info.n_local, info.n_global
 
     @property

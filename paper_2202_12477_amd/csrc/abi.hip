@@ -32,7 +32,9 @@ void free_mesh(hb_mesh_s *m)
     if (!m) return;
     free_cg(m);
     if (m->map) (void)hipFree(m->map);
-    for (double *p : {m->geo, m->D, m->xi, m->w})
+    for (double *p : {m->geo, m->D, m->xi, m->w, m->yl})
+        if (p) (void)hipFree(p);
+    for (uint32_t *p : {m->zt_off, m->zt_idx})
         if (p) (void)hipFree(p);
     for (float *p : {m->geo32, m->D32})
         if (p) (void)hipFree(p);
@@ -88,7 +90,10 @@ hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out)
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: element counts must be >= 1");
     if (!(d.jitter >= 0.0 && d.jitter < 0.5)) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: jitter must be in [0, 0.5)");
     if (d.mass != HB_MASS_GWJ && d.mass != HB_MASS_INVDEG) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: bad mass kind");
-    if (d.flags & ~(HB_MESH_FP32 | HB_MESH_DIRICHLET)) return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: unknown flag");
+    if (d.flags & ~(HB_MESH_FP32 | HB_MESH_DIRICHLET | HB_MESH_GATHER))
+        return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: unknown flag");
+    if ((d.flags & HB_MESH_GATHER) && (d.flags & HB_MESH_FP32))
+        return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: the two-phase operator is FP64 only (HB_MESH_GATHER excludes HB_MESH_FP32)");
     if ((d.flags & HB_MESH_DIRICHLET) && ((int64_t)d.nx * d.N < 2 || (int64_t)d.ny * d.N < 2 || (int64_t)d.nz * d.N < 2))
         return fail(HB_ERR_INVALID_ARG, "hb_mesh_create: a Dirichlet box needs interior nodes (n*N >= 2)");
     const int64_t n1 = d.N + 1;
@@ -125,6 +130,10 @@ hb_status hb_mesh_create(const hb_mesh_desc *desc, void *stream, hb_mesh *out)
         return hip_fail(e, "hb_mesh_create: copy of the 1D basis");
     }
     if ((st = build_geometry(m, s))) {
+        free_mesh(m);
+        return st;
+    }
+    if ((d.flags & HB_MESH_GATHER) && (st = build_gather(m, s))) {
         free_mesh(m);
         return st;
     }
@@ -201,6 +210,7 @@ hb_status hb_ax(hb_mesh m, double lambda, const double *dev_x, double *dev_y, vo
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(HB_ERR_INVALID_ARG, "hb_ax: lambda must be finite and > 0");
     if (dev_x == dev_y) return fail(HB_ERR_INVALID_ARG, "hb_ax: x and y must not alias");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (m->desc.flags & HB_MESH_GATHER) return launch_ax_two_phase(m, lambda, dev_x, dev_y, nullptr, nullptr, true, s);
     hb_status st = launch_zero(dev_y, m->NG, s);
     if (st) return st;
     return launch_ax(m, lambda, dev_x, dev_y, nullptr, nullptr, s);

@@ -79,6 +79,7 @@ int ax_schedule_epoch() { return g_epoch.load(); }
 hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
                     hipStream_t s)
 {
+    if (m->desc.flags & HB_MESH_GATHER) return launch_ax_two_phase(m, lambda, x, y, partial, st, false, s);
     const bool d = (m->desc.flags & HB_MESH_DIRICHLET) != 0;
     switch (m->N) {
 #define HB_CASE(n) \
@@ -141,7 +142,11 @@ TileWalk ax_walk_for(int N, int64_t nx, int64_t ny, int64_t nz, int sched)
     }
 }
 
-int ax_blocks(const hb_mesh_s *m, bool fp32) { return ax_grid_for(m->N, m->E, ax_schedule(m->N, fp32)); }
+int ax_blocks(const hb_mesh_s *m, bool fp32)
+{
+    if (!fp32 && (m->desc.flags & HB_MESH_GATHER)) return ax_local_blocks(m);
+    return ax_grid_for(m->N, m->E, ax_schedule(m->N, fp32));
+}
 
 int ax_blocks_max(const hb_mesh_s *m)
 {

@@ -116,7 +116,7 @@ __device__ inline void atomic_add(gptr<T> p, T v)
 // Every thread of the block must call it (it synchronises the block).
 // (Always inlined: the single-problem and the batched kernel both call it, and
 // an out-of-line call would spill the whole register set.)
-template <int N, bool DOT, typename T, int V, bool MASK>
+template <int N, bool DOT, typename T, int V, bool MASK, bool LOCAL = false>
 __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
                                gptr<const T> __restrict__ geo, gptr<const T> __restrict__ Dm, T lambda,
                                gptr<const double> __restrict__ x, gptr<T> __restrict__ y,
@@ -291,6 +291,16 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
 #pragma unroll
         for (int c = 0; c < n1; ++c) pin(yv[c]);
     }
+    if constexpr (LOCAL) {
+        // the two-phase form: y is the unassembled local vector y_L, [E][(N+1)^3]
+        // in the map's order, written with plain coalesced stores (the gather
+        // that assembles it reads it back while it is still in the caches)
+        if (active) {
+            gptr<T> yl = y + eo * np3 + ab;
+#pragma unroll
+            for (int c = 0; c < n1; ++c) yl[c * np2] = yv[c];
+        }
+    } else {
     // assemble through Z^T.  Where several elements share a wave, the a = 0 face
     // node of an element is the a = N face node of the previous one whenever the
     // two are neighbours along r: the lanes holding them then see the same index,
@@ -326,6 +336,7 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             for (int c = 0; c < n1; ++c) atomic_add(&y[idx[c]], yv[c]);
         }
     }
+    }
     if constexpr (DOT) {
         // sum_e x_e . y_e = x . Z^T y_L = x . A x, accumulated in FP64
         double v = 0.0;
@@ -351,6 +362,23 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
     }
     ax_tile<N, DOT, T, V, MASK>(E, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), to_global(map), to_global(geo), to_global(Dm),
                           lambda, to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));
+}
+
+// First phase of the two-phase operator: y_L = (S_L + lambda C) Z x per element
+// (no assembly), with the same tiles and optional p.Ap partials as ax_kernel.
+template <int N, bool DOT, int V, bool MASK>
+__global__ __launch_bounds__((AxShape<N, V>::threads))
+__attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_local_kernel(
+    int64_t E, TileWalk walk, const int32_t *__restrict__ map, const double *__restrict__ geo,
+    const double *__restrict__ Dm, double lambda, const double *__restrict__ x, double *__restrict__ yl,
+    double *__restrict__ partial, const CgState *__restrict__ st)
+{
+    if constexpr (DOT) {
+        if (st->done | st->pending) return;
+    }
+    ax_tile<N, DOT, double, V, MASK, true>(E, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), to_global(map),
+                                           to_global(geo), to_global(Dm), lambda, to_global(x), to_global(yl),
+                                           to_global(DOT ? partial + blockIdx.x : partial));
 }
 
 // Values read from a work list or a problem table are the same for the whole
@@ -462,6 +490,25 @@ hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambd
     });
 }
 
+// The first phase under the degree's default FP64 schedule (V): y_L for every
+// local node of the mesh.
+template <int N, int V, bool MASK>
+hb_status launch_ax_local_n(const hb_mesh_s *m, double lambda, const double *x, double *yl, double *partial,
+                            CgState *st, hipStream_t s)
+{
+    const int grid = ax_grid<N, V>(m->E);
+    if (grid == 0) return HB_OK;
+    const TileWalk walk = make_walk(m->desc.nx, m->desc.ny, m->desc.nz, AxShape<N, V>::epb);
+    if (st)
+        ax_local_kernel<N, true, V, MASK><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, m->geo, m->D,
+                                                                                lambda, x, yl, partial, st);
+    else
+        ax_local_kernel<N, false, V, MASK><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, m->geo, m->D,
+                                                                                 lambda, x, yl, nullptr, nullptr);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
 template <int N, bool MASK>
 hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
                             hipStream_t s)
@@ -525,4 +572,17 @@ hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int
     {                                                                                                          \
         return launch_batch_ax_n<n, true>(D, fp32, it, ni, pr, s);                                             \
     }                                                                                                          \
+    }
+
+// The first phase of the two-phase operator for one degree (plain and
+// Dirichlet meshes), under schedule v, in a translation unit of its own.
+#define HB_AX_INSTANCE_LOCAL(n, v)                                                                             \
+    namespace hb {                                                                                             \
+    hb_status launch_ax_local_##n(const hb_mesh_s *m, double l, const double *x, double *yl, double *p,        \
+                                  CgState *st, hipStream_t s)                                                  \
+    {                                                                                                          \
+        return (m->desc.flags & HB_MESH_DIRICHLET) ? launch_ax_local_n<n, v, true>(m, l, x, yl, p, st, s)      \
+                                                   : launch_ax_local_n<n, v, false>(m, l, x, yl, p, st, s);    \
+    }                                                                                                          \
+    int ax_local_grid_##n(int64_t E) { return ax_grid<n, v>(E); }                                              \
     }

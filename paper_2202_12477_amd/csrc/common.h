@@ -151,6 +151,11 @@ struct hb_mesh_s {
     double *xi = nullptr, *w = nullptr;  // device copies of the GLL nodes and weights
     float *geo32 = nullptr;   // FP32 copy of geo (HB_MESH_FP32), rounded once
     float *D32 = nullptr;     // FP32 copy of D
+    // two-phase operator (HB_MESH_GATHER): the local output y_L [E][(N+1)^3] and
+    // Z^T as CSR rows (row g: the local nodes mapped to g, ascending)
+    double *yl = nullptr;
+    uint32_t *zt_off = nullptr;  // [N_G + 1]
+    uint32_t *zt_idx = nullptr;  // [local nodes that carry a DOF]
     double h_xi[hb::kMaxN + 1], h_w[hb::kMaxN + 1], h_D[(hb::kMaxN + 1) * (hb::kMaxN + 1)];
     hb::CgWork cg;
     size_t device_bytes = 0;
@@ -171,6 +176,13 @@ hb_status launch_rhs(int64_t n, uint64_t seed, double *b, hipStream_t s);
 // writes its share of sum_e x_e . y_e (= x . A x) to partial[block].
 hb_status launch_ax(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial, CgState *st,
                     hipStream_t s);
+// The two-phase operator of an HB_MESH_GATHER mesh (gather.hip): y_L by the
+// element kernel, then y (+)= Z^T y_L by a deterministic gather (overwrite:
+// y = Z^T y_L, no zeroing needed).  launch_ax routes such meshes here (adding).
+hb_status launch_ax_two_phase(const hb_mesh_s *m, double lambda, const double *x, double *y, double *partial,
+                              CgState *st, bool overwrite, hipStream_t s);
+int ax_local_blocks(const hb_mesh_s *m);
+hb_status build_gather(hb_mesh_s *m, hipStream_t s);
 // The FP32 operator (mesh built with HB_MESH_FP32): x FP64, y FP32.
 hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float *y, double *partial, CgState *st,
                       hipStream_t s);

@@ -551,6 +551,8 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
             return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": bad pointers");
         if (!(lambdas[i] > 0.0) || !std::isfinite(lambdas[i]))
             return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": lambda must be > 0");
+        if (meshes[i]->desc.flags & HB_MESH_GATHER)
+            return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: two-phase (HB_MESH_GATHER) meshes are solved one at a time");
         if (mixed && !meshes[i]->geo32)
             return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + " has no FP32 data");
         for (int k = 0; k < i; ++k)
@@ -632,6 +634,8 @@ hb_status hb_engine_submit(hb_engine e, const hb_mesh_desc *desc, double lambda,
     if (desc->N < 1 || desc->N > kMaxN || desc->nx < 1 || desc->ny < 1 || desc->nz < 1 ||
         !(desc->jitter >= 0.0 && desc->jitter < 0.5) || (desc->mass != HB_MASS_GWJ && desc->mass != HB_MASS_INVDEG))
         return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: bad mesh descriptor");
+    if (desc->flags & HB_MESH_GATHER)
+        return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: the engine runs the fused operator (no HB_MESH_GATHER)");
     if ((desc->flags & HB_MESH_DIRICHLET) &&
         ((int64_t)desc->nx * desc->N < 2 || (int64_t)desc->ny * desc->N < 2 || (int64_t)desc->nz * desc->N < 2))
         return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: a Dirichlet box needs interior nodes (n*N >= 2)");

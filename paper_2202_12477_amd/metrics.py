@@ -40,6 +40,13 @@ def ax_bytes_fused(NG: int, NL: int, word: int = 8) -> float:
     return 2.0 * word * NG + (4.0 + 7.0 * word) * NL
 
 
+def ax_bytes_two_phase(NG: int, NL: int) -> float:
+    """The two-phase operator: the element kernel (x, map, geometry, y_L written:
+    8 N_G + 68 N_L), then the gather (y_L read, 4-byte CSR index per local node,
+    4-byte row offsets, y written: 12 N_G + 12 N_L)."""
+    return ax_bytes_paper(NG, NL) + 12.0 * NG + 12.0 * NL
+
+
 def ax_bytes_f32(NG: int, NL: int) -> float:
     """FP32 operator: FP64 x read, FP32 y written, int32 map, 7 FP32 geometric values."""
     return 8.0 * NG + 4.0 * NG + (4.0 + 7.0 * 4.0) * NL

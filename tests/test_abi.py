@@ -55,7 +55,7 @@ def _desc(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(N=0), dict(N=16), dict(nx=0), dict(nz=-1), dict(jitter=0.5),
-                                 dict(jitter=-0.1), dict(jitter=float("nan")), dict(mass=2), dict(flags=4),
+                                 dict(jitter=-0.1), dict(jitter=float("nan")), dict(mass=2), dict(flags=8), dict(flags=hb.MESH_GATHER | hb.MESH_FP32),
                                  dict(flags=hb.MESH_DIRICHLET, nx=1, N=1), dict(flags=3, ny=1, N=1),
                                  dict(nx=2000, ny=2000, nz=2000, N=15)])
 def test_mesh_create_rejects_bad_descriptors(L, bad):
