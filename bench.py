@@ -127,6 +127,84 @@ def paper_workload(hb, torch, metrics, B, n=50, N=7):
     return out
 
 
+def jacobi_vs_plain(hb, torch, n=32, N=7, jitter=0.2, rtol=1e-8):
+    """Jacobi-preconditioned CG beside plain CG on a deformed Dirichlet box
+    (n^3 elements with jittered vertices, N=7, FP64, U[-1,1) forcing): the cost
+    of one iteration (100 fixed iterations each) and the time to a relative
+    residual of rtol (the diagonal is computed once per mesh and lambda, timed
+    on its own)."""
+    m = hb.Mesh(n, n, n, N, jitter=jitter, seed=5, dirichlet=True)
+    b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+    hb.rhs_uniform(b, 7)
+    x = torch.empty_like(b)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(**kw):
+        ev[0].record()
+        res = m.cg(1.0, b, x, history=False, **kw)
+        ev[1].record()
+        ev[1].synchronize()
+        return res, ev[0].elapsed_time(ev[1]) * 1e-3
+
+    m.cg(1.0, b, x, max_iter=5, fixed_iters=True, history=False)
+    _, t_first = timed(max_iter=1, fixed_iters=True, precond=hb.PRECOND_JACOBI)  # diagonal + one iteration
+    _, t_one = timed(max_iter=1, fixed_iters=True, precond=hb.PRECOND_JACOBI)
+    out = {"workload": f"deformed Dirichlet box {n}^3 (vertex jitter {jitter}), N={N}, {m.NG} DOFs, lambda=1",
+           "diag_ms": round(max(t_first - t_one, 0.0) * 1e3, 3)}
+    for name, pc in (("cg", hb.PRECOND_NONE), ("pcg", hb.PRECOND_JACOBI)):
+        res, t = timed(max_iter=CG_ITERS, fixed_iters=True, precond=pc)
+        assert res.iters == CG_ITERS and res.status == hb.HB_OK, res
+        out[f"{name}_ms_per_iter"] = round(t / CG_ITERS * 1e3, 4)
+        res, t = timed(max_iter=20000, fixed_iters=False, rtol=rtol, precond=pc)
+        assert res.status == hb.HB_OK, res
+        out[f"{name}_iters_to_{rtol:g}"] = res.iters
+        out[f"{name}_s_to_{rtol:g}"] = round(t, 4)
+    out["time_to_solution_speedup"] = round(out[f"cg_s_to_{rtol:g}"] / out[f"pcg_s_to_{rtol:g}"], 3)
+    m.close()
+    return out
+
+
+def two_phase_vs_fused(hb, torch, metrics, B, n, N, dirichlet, label):
+    """The two-phase operator (element kernel writing y_L, then the CSR gather;
+    HB_MESH_GATHER) beside the fused one on the same mesh: y = A x (50 calls
+    each) and 100 fixed CG iterations, FP64.  Both results are checked against
+    each other, and two-phase results for bit-identity between repeats."""
+    out = {"workload": label}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ys = {}
+    for name, gather in (("fused", False), ("two_phase", True)):
+        m = hb.Mesh(n, n, n, N, dirichlet=dirichlet, gather=gather)
+        b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+        hb.rhs_uniform(b, 3)
+        y, y2, x = torch.empty_like(b), torch.empty_like(b), torch.empty_like(b)
+        m.ax(1.0, b, y2)
+        m.cg(1.0, b, x, max_iter=10, fixed_iters=True, history=False)
+        ev[0].record()
+        for _ in range(AX_CALLS):
+            m.ax(1.0, b, y)
+        ev[1].record()
+        res = m.cg(1.0, b, x, max_iter=CG_ITERS, fixed_iters=True, history=False)
+        ev[2].record()
+        ev[2].synchronize()
+        assert res.iters == CG_ITERS and res.status == hb.HB_OK, res
+        t_ax = ev[0].elapsed_time(ev[1]) * 1e-3 / AX_CALLS
+        t_cg = ev[1].elapsed_time(ev[2]) * 1e-3 / CG_ITERS
+        nbytes = (metrics.ax_bytes_two_phase if gather else metrics.ax_bytes_fused)(m.NG, m.NL)
+        out[f"{name}_ax_us"] = round(t_ax * 1e6, 1)
+        out[f"{name}_ax_gdofs"] = round(m.NG / t_ax / 1e9, 2)
+        out[f"{name}_ax_bytes"] = int(nbytes)
+        out[f"{name}_ax_frac_of_stream"] = round(nbytes / t_ax / 1e9 / B, 4)
+        out[f"{name}_cg_ms_per_iter"] = round(t_cg * 1e3, 4)
+        if gather:
+            out["two_phase_bit_identical_repeats"] = bool(torch.equal(y, y2))
+        ys[name] = y
+        m.close()
+    d = torch.linalg.vector_norm(ys["two_phase"] - ys["fused"]) / torch.linalg.vector_norm(ys["fused"])
+    out["rel_diff_two_phase_vs_fused"] = float(f"{d.item():.3e}")
+    assert d.item() <= 1e-12, d.item()
+    return out
+
+
 def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
     """The 64 uneven problems: one-by-one FP64 CG vs the batched solver (FP64, and
     FP32 operator with FP64 residual replacement with plain launches and with
@@ -194,6 +272,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solves comparison")
+    ap.add_argument("--no-jacobi", action="store_true", help="skip the Jacobi-preconditioned CG comparison")
+    ap.add_argument("--no-two-phase", action="store_true", help="skip the two-phase operator comparison")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="arrivals of the serving trace to replay (0 skips the serving comparison)")
     args = ap.parse_args()
@@ -285,6 +365,13 @@ def main():
     m.close()
     del b, y, yk, x
     out["paper_workload"] = paper_workload(hb, torch, metrics, B)
+    if not args.no_jacobi:
+        out["jacobi"] = jacobi_vs_plain(hb, torch)
+    if not args.no_two_phase:
+        out["two_phase"] = [
+            two_phase_vs_fused(hb, torch, metrics, B, case.nx, case.N, False,
+                               f"{case.nx}^3 affine box, N={case.N}, {NG} DOFs"),
+            two_phase_vs_fused(hb, torch, metrics, B, 50, 7, True, "Dirichlet box 50^3, N=7, 42508549 DOFs")]
     if not args.no_batch:
         out["batch"] = batched_vs_sequential(hb, torch, inputs)
     if args.serve_requests > 0:

@@ -1,14 +1,15 @@
 """Profiling driver for rocprofv3: operator launches plus a streaming kernel of known traffic.
 
-Runs `--launches` applications of the operator (y += A x, hb_ax_add; or the FP32
-operator with --fp32) on one synthetic box, then as many launches of the 8:1
+Runs `--launches` applications of the operator (y += A x, hb_ax_add; the FP32
+operator with --fp32; the two-phase operator, y = A x on an HB_MESH_GATHER
+mesh, with --gather) on one synthetic box, then as many launches of the 8:1
 streaming probe (hb_stream_probe over 2^25 outputs: 8 * 2^25 doubles read and
 2^25 written per launch, 2.4 GB).  Under `rocprofv3 --pmc FETCH_SIZE` (then
 WRITE_SIZE, in a run of its own) the probe's counter values per launch, divided
 by its known bytes, give the factor that turns the counters into HBM bytes for
 the operator's launches.
 
-  python -m paper_2202_12477_amd.profile_ax [--case box32_N7_affine | sweepN] [--launches K] [--fp32]
+  python -m paper_2202_12477_amd.profile_ax [--case box32_N7_affine | sweepN] [--launches K] [--fp32 | --gather]
 """
 from __future__ import annotations
 
@@ -24,7 +25,10 @@ def main():
     ap.add_argument("--case", default="box32_N7_affine", help="box32_N7_affine, box4_N3_jitter or sweep<N>")
     ap.add_argument("--launches", type=int, default=10)
     ap.add_argument("--fp32", action="store_true")
+    ap.add_argument("--gather", action="store_true")
     args = ap.parse_args()
+    if args.fp32 and args.gather:
+        ap.error("the two-phase operator is FP64 only")
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import torch
@@ -36,20 +40,24 @@ def main():
         c = inputs.order_sweep_case(int(args.case[5:]))
     else:
         c = {k.name: k for k in (inputs.PLAIN_SMALL, inputs.PLAIN_LARGE)}[args.case]
-    m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=args.fp32)
+    m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=args.fp32, gather=args.gather)
     b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
     hb.rhs_uniform(b, c.rhs_seed)
     if args.fp32:
         y = torch.zeros(m.NG, dtype=torch.float32, device="cuda")
         for _ in range(args.launches):
             m.ax_f32(c.lam, b, y)
+    elif args.gather:
+        y = torch.empty_like(b)
+        for _ in range(args.launches):
+            m.ax(c.lam, b, y)
     else:
         y = torch.zeros_like(b)
         for _ in range(args.launches):
             m.ax_add(c.lam, b, y)
     torch.cuda.synchronize()
     print(f"operator {c.name} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={args.launches} "
-          f"{'fp32' if args.fp32 else 'fp64'}", flush=True)
+          f"{'fp32' if args.fp32 else 'fp64'}{' two-phase' if args.gather else ''}", flush=True)
     m.close()
     del b, y
     inp = torch.ones(8 * STREAM_N, dtype=torch.float64, device="cuda")
