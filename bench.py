@@ -206,9 +206,10 @@ def two_phase_vs_fused(hb, torch, metrics, B, n, N, dirichlet, label):
 
 
 def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
-    """The 64 uneven problems: one-by-one FP64 CG vs the batched solver (FP64, and
-    FP32 operator with FP64 residual replacement with plain launches and with
-    25-iteration segments replayed from captured graphs), all to rtol; solves/s."""
+    """The 64 uneven problems: one-by-one FP64 CG vs the batched solver (FP64, FP64
+    with the Jacobi preconditioner, and FP32 operator with FP64 residual
+    replacement with plain launches and with 25-iteration segments replayed from
+    captured graphs), all to rtol; solves/s."""
     cases = inputs.batched_cases()
     meshes, bs = [], []
     for c in cases:
@@ -228,13 +229,14 @@ def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
             iters += r.iters
         return iters
 
-    def batch(prec, graph_k=0):
+    def batch(prec, graph_k=0, precond=hb.PRECOND_NONE):
         st, res = hb.batch_solve(meshes, [c.lam for c in cases], bs, xs, max_iter=100000, rtol=rtol, prec=prec,
-                                 graph_k=graph_k)
+                                 graph_k=graph_k, precond=precond)
         assert st == hb.HB_OK, [r.status for r in res]
         return sum(r.iters for r in res)
 
     for name, fn in (("sequential_fp64", seq), ("batched_fp64", lambda: batch(hb.PREC_FP64)),
+                     ("batched_fp64_jacobi", lambda: batch(hb.PREC_FP64, precond=hb.PRECOND_JACOBI)),
                      ("batched_fp32rr", lambda: batch(hb.PREC_FP32_RR)),
                      ("batched_fp32rr_graphs", lambda: batch(hb.PREC_FP32_RR, graph_k=25))):
         torch.cuda.synchronize()

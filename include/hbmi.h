@@ -186,8 +186,8 @@ typedef struct {
                             hb_batch_solve: > 0 makes each segment graph_k iterations long (instead of
                             check_every) and replays it from a captured graph until the set of running
                             problems changes. At most 4096. */
-    int32_t precond;     /* hb_precond; HB_PRECOND_JACOBI with HB_PREC_FP64 in hb_cg_solve only (hb_batch_solve
-                            and the engine take HB_PRECOND_NONE) */
+    int32_t precond;     /* hb_precond; HB_PRECOND_JACOBI with HB_PREC_FP64 only (hb_cg_solve and hb_batch_solve;
+                            the engine runs unpreconditioned CG) */
 } hb_cg_opts;
 
 typedef struct {

@@ -31,10 +31,11 @@ __global__ __launch_bounds__(kFinThreads) void batch_beta_kernel(const int32_t *
                                                                 const BatchProb *__restrict__ probs)
 {
     const BatchProb &P = probs[plist[blockIdx.x]];
-    beta_step(P.part_vec, P.vec_chunks, P.st, P.rho, P.hist);
+    beta_step(P.part_vec, P.vec_chunks, P.st, P.rho, P.hist, P.inv != nullptr);
 }
 
-// r -= alpha Ap on one chunk; the chunk's partial of r.r.
+// r -= alpha Ap on one chunk; the chunk's partial of r.r (Jacobi: of r.z, z =
+// inv r, and of r.r in the second half of the partials).
 __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkItem *__restrict__ items,
                                                                     const BatchProb *__restrict__ probs)
 {
@@ -57,6 +58,23 @@ __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkI
             r[i] = ri;
             rr += ri * ri;
         }
+    } else if (uniform(P.inv)) {
+        const auto Ap = to_global(uniform(P.Ap));
+        const auto inv = to_global(uniform(P.inv));
+        double rz = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const double ri = r[i] - alpha * Ap[i];
+            r[i] = ri;
+            rr += ri * ri;
+            rz += ri * (inv[i] * ri);
+        }
+        rr = block_sum(rr, red);
+        rz = block_sum(rz, red);
+        if (threadIdx.x == 0) {
+            to_global(uniform(P.part_vec))[chunk] = rz;
+            to_global(uniform(P.part_vec))[uniform(P.vec_chunks) + chunk] = rr;
+        }
+        return;
     } else {
         const auto Ap = to_global(uniform(P.Ap));
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
@@ -69,7 +87,7 @@ __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkI
     if (threadIdx.x == 0) to_global(uniform(P.part_vec))[chunk] = rr;
 }
 
-// x += alpha p; p = r + beta p; Ap = 0 on one chunk.
+// x += alpha p; p = r + beta p (Jacobi: p = inv r + beta p); Ap = 0 on one chunk.
 __global__ __launch_bounds__(kVecThreads) void batch_update_kernel(const WorkItem *__restrict__ items,
                                                                   const BatchProb *__restrict__ probs)
 {
@@ -85,10 +103,19 @@ __global__ __launch_bounds__(kVecThreads) void batch_update_kernel(const WorkIte
     const auto x = to_global(uniform(P.x));
     const auto p = to_global(uniform(P.p));
     const auto r = to_global(uniform(P.r));
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const double pi = p[i];
-        x[i] += alpha * pi;
-        p[i] = r[i] + beta * pi;
+    if (uniform(P.inv)) {
+        const auto inv = to_global(uniform(P.inv));
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const double pi = p[i];
+            x[i] += alpha * pi;
+            p[i] = inv[i] * r[i] + beta * pi;
+        }
+    } else {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const double pi = p[i];
+            x[i] += alpha * pi;
+            p[i] = r[i] + beta * pi;
+        }
     }
     if (uniform(P.use32)) {
         const auto Ap = to_global(uniform(P.Ap32));

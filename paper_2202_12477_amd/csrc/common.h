@@ -85,6 +85,7 @@ struct BatchProb {
     int32_t N, ax_tiles, vec_chunks, use32;  // use32: the operator of this problem is the FP32 one
     int32_t nx, ny, nz;                      // the box (host side: the order of the operator tiles)
     int32_t dirichlet;                       // a Dirichlet box (host side: its class of operator launches)
+    const double *inv;                       // Jacobi: 1 / diag(A) (nullptr: no preconditioner)
 };
 
 // A unit of batched work: problem index and tile (operator) or chunk (vectors).

@@ -100,8 +100,15 @@ class BatchRunner {
         q.opts = o;
         q.mixed = mixed;
         const double rtol = o.fixed_iters ? -1.0 : o.rtol;
-        if ((st = cg_start(m, lambda, b, x, states_ + i, o.x0_zero, o.max_iter, rtol, mixed, s_))) return st;
-        HB_HIP(hipMemcpyAsync(h_rho_ + i, m->cg.rho, sizeof(double), hipMemcpyDeviceToHost, s_));
+        const bool pc = o.precond == HB_PRECOND_JACOBI;
+        if (pc && (st = ensure_jacobi(m, lambda, s_))) return st;
+        m->cg.pc = pc;  // the first step (r0, z0 = inv r0, p0 = z0, r0.z0)
+        st = cg_start(m, lambda, b, x, states_ + i, o.x0_zero, o.max_iter, rtol, mixed, s_);
+        m->cg.pc = false;
+        if (st) return st;
+        // mixed: r0.r0 (the replacement's start); FP64: ||r0|| from the residual
+        // history (r0.r0 is not kept when the iteration is preconditioned)
+        HB_HIP(hipMemcpyAsync(h_rho_ + i, mixed ? m->cg.rho : m->cg.hist, sizeof(double), hipMemcpyDeviceToHost, s_));
         CgWork &w = m->cg;
         BatchProb &P = h_probs_[i];
         P.map = m->map;
@@ -130,6 +137,7 @@ class BatchRunner {
         P.ax_tiles = ax_blocks(m, mixed);  // recomputed with the lists (schedule, precision)
         P.vec_chunks = static_cast<int32_t>((m->NG + kBatchChunk - 1) / kBatchChunk);
         P.use32 = mixed ? 1 : 0;
+        P.inv = pc ? w.jinv : nullptr;
         dirty_ = true;
         return HB_OK;
     }
@@ -284,7 +292,7 @@ class BatchRunner {
             } else if (hs.done) {
                 q.result = hb_cg_result{};
                 q.result.status = hs.status;
-                q.result.res0 = q.result.res = std::sqrt(h_rho_[i]);
+                q.result.res0 = q.result.res = h_rho_[i];
                 q.result.bnorm = std::sqrt(hs.bb);
                 q.finished = true;
             }
@@ -397,7 +405,7 @@ class BatchRunner {
             if (!stopped) continue;
             if (!q.mixed) {
                 done64.push_back(i);
-                HB_HIP(hipMemcpyAsync(h_norms_ + i, q.mesh->cg.rho + hs.iters, sizeof(double),
+                HB_HIP(hipMemcpyAsync(h_norms_ + i, q.mesh->cg.hist + hs.iters, sizeof(double),
                                       hipMemcpyDeviceToHost, s_));
                 continue;
             }
@@ -418,8 +426,8 @@ class BatchRunner {
             q.result = hb_cg_result{};
             q.result.iters = hs.iters;
             q.result.status = hs.status;
-            q.result.res0 = std::sqrt(h_rho_[i]);
-            q.result.res = std::sqrt(h_norms_[i]);
+            q.result.res0 = h_rho_[i];
+            q.result.res = h_norms_[i];
             q.result.bnorm = std::sqrt(hs.bb);
             q.finished = true;
             dirty_ = true;
@@ -544,8 +552,10 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
     if (!fixed && !(opts->rtol >= 0.0)) return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: rtol must be >= 0");
     if (opts->graph_k < 0 || opts->graph_k > 4096)
         return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: graph_k must be in [0, 4096]");
-    if (opts->precond != HB_PRECOND_NONE)
-        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: no preconditioner is available here");
+    if (opts->precond != HB_PRECOND_NONE && opts->precond != HB_PRECOND_JACOBI)
+        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: unknown preconditioner");
+    if (opts->precond == HB_PRECOND_JACOBI && opts->prec != HB_PREC_FP64)
+        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: the Jacobi preconditioner is available with HB_PREC_FP64 only");
     for (int i = 0; i < nprob; ++i) {
         if (!meshes[i] || !dev_b[i] || !dev_x[i] || dev_b[i] == dev_x[i])
             return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": bad pointers");

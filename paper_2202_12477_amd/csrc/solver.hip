@@ -40,8 +40,10 @@ hb_status ensure_cg(hb_mesh_s *m, int max_iter, bool mixed, bool refine)
 {
     CgWork &w = m->cg;
     const int need_ax = ax_blocks_max(m);  // any schedule of either precision
-    // three partial arrays for the first step of the preconditioned iteration
-    const int need_vec = static_cast<int>(std::max<int64_t>(3 * vec_blocks(m->NG), (m->NG + kBatchChunk - 1) / kBatchChunk));
+    // three partial arrays for the first step of the preconditioned iteration,
+    // two per chunk for the batched preconditioned one
+    const int need_vec = static_cast<int>(
+        std::max<int64_t>(3 * vec_blocks(m->NG), 2 * ((m->NG + kBatchChunk - 1) / kBatchChunk)));
     if (w.r && w.n == m->NG && w.hist_len >= max_iter + 1 && w.part_ax_len >= need_ax &&
         w.part_vec_len >= need_vec && (!mixed || w.Ap32) && (!refine || w.rout))
         return HB_OK;

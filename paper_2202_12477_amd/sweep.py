@@ -5,9 +5,12 @@ For every degree N: the FP64 operator (hb_ax_add) and the FP32 operator
 launching stream, as algorithmic GB/s and GDOF/s; the FP32 operator's relative
 difference from the FP64 one on the same input; and with --solve, FP64 CG vs
 the two mixed-precision solvers to a relative residual (solves timed end to
-end, true residual reported by each solver).  One JSON line per degree.
+end, true residual reported by each solver); with --two-phase, y = A x by the
+two-phase operator (HB_MESH_GATHER: element kernel, then the gather) beside
+the fused hb_ax on the same mesh, in the paper's operator GFLOP/s.  One JSON
+line per degree.
 
-  python -m paper_2202_12477_amd.sweep [--degrees 1 2 ...] [--reps 20] [--solve] [--rtol 1e-10]
+  python -m paper_2202_12477_amd.sweep [--degrees 1 2 ...] [--reps 20] [--solve] [--rtol 1e-10] [--two-phase]
 """
 from __future__ import annotations
 
@@ -24,6 +27,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--solve", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--two-phase", action="store_true")
     args = ap.parse_args()
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -63,6 +67,20 @@ def main():
                "fp64_gdofs": round(m.NG / t64 / 1e9, 2), "fp64_gflops": round(metrics.ax_flops(m.E, N) / t64 / 1e9, 1),
                "fp32_us": round(t32 * 1e6, 1), "fp32_GBs": round(b32 / t32 / 1e9, 1),
                "fp32_gdofs": round(m.NG / t32 / 1e9, 2), "fp32_vs_fp64_rel": float(f"{diff:.3e}")}
+        if args.two_phase:
+            g = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, gather=True)
+            yg = torch.empty_like(b)
+            tf = timed(lambda: m.ax(c.lam, b, y), args.reps)
+            tg = timed(lambda: g.ax(c.lam, b, yg), args.reps)
+            g.ax(c.lam, b, yg)
+            m.ax(c.lam, b, y)
+            fl = metrics.ax_flops(m.E, N)
+            out["two_phase"] = {"fused_ax_us": round(tf * 1e6, 1), "fused_gflops": round(fl / tf / 1e9, 1),
+                                "two_phase_us": round(tg * 1e6, 1), "two_phase_gflops": round(fl / tg / 1e9, 1),
+                                "two_phase_GBs": round(metrics.ax_bytes_two_phase(m.NG, m.NL) / tg / 1e9, 1),
+                                "rel_diff": float(f"{float(torch.linalg.norm(yg - y) / torch.linalg.norm(y)):.3e}")}
+            g.close()
+            del yg
         if args.solve:
             x = torch.empty_like(b)
             for name, prec in (("fp64", hb.PREC_FP64), ("fp32_ir", hb.PREC_FP32_IR), ("fp32_rr", hb.PREC_FP32_RR)):

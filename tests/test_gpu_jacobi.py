@@ -3,7 +3,8 @@ against the oracle's preconditioned CG through the C ABI: fixed-iteration
 residual histories within the envelope of the oracle's two summation orders
 (plain box, Dirichlet box, graph replay), tolerance solves checked by their
 true residual under the oracle's FP64 operator, fewer iterations than the
-unpreconditioned solve on a deformed mesh, and the argument checks."""
+unpreconditioned solve on a deformed mesh, batched PCG over uneven problems
+(hb_batch_solve, with and without graph replay), and the argument checks."""
 import sys
 
 import numpy as np
@@ -39,6 +40,10 @@ def pcg_bar(ref, b, lam, iters):
     h = ref.pcg(b, lam, fixed_iters=iters, compensated=True)["res"]
     alt = ref.pcg(b, lam, fixed_iters=iters, compensated=False)["res"]
     return h, np.maximum(1e-10, 10.0 * np.abs(h - alt) / np.abs(h))
+
+
+def relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def ratio_to_bar(got, ref, bar):
@@ -130,7 +135,10 @@ def test_pcg_argument_checks():
     with pytest.raises(hb.HbError):
         m.cg(1.0, b, x, max_iter=5, precond=-1)
     with pytest.raises(hb.HbError):
-        hb.batch_solve([m], [1.0], [b], [x], max_iter=5, precond=hb.PRECOND_JACOBI)
+        hb.batch_solve([m], [1.0], [b], [x], max_iter=50, rtol=1e-8, prec=hb.PREC_FP32_RR,
+                       precond=hb.PRECOND_JACOBI)
+    with pytest.raises(hb.HbError):
+        hb.batch_solve([m], [1.0], [b], [x], max_iter=5, precond=3)
     # an unpreconditioned solve after a preconditioned one is plain CG again
     res = m.cg(1.0, b, x, max_iter=10, precond=hb.PRECOND_JACOBI)
     assert res.status == hb.HB_OK
@@ -139,3 +147,42 @@ def test_pcg_argument_checks():
     h = ref.cg(oracle.rhs(ref.NG, 3), 1.0, fixed_iters=10)["res"]
     assert np.allclose(plain.history, h, rtol=1e-9, atol=0)
     m.close()
+
+
+@pytest.mark.parametrize("graph_k", [0, 6])
+def test_batched_pcg(graph_k):
+    """hb_batch_solve with the Jacobi preconditioner over uneven problems (plain
+    and Dirichlet boxes, N = 3..9): each reaches 1e-10 on its true residual in the
+    oracle's PCG iteration count (+-2), and 40 fixed iterations match the
+    one-problem PCG solution."""
+    say(f"[case] batched PCG graph_k={graph_k}")
+    shapes = [(3, 3, 3, 3, False), (2, 3, 2, 7, True), (2, 2, 2, 9, False), (4, 2, 3, 5, True)]
+    ms, refs, bs, bhs = [], [], [], []
+    for i, (nx, ny, nz, N, d) in enumerate(shapes):
+        m, ref, b, bh = setup(nx, ny, nz, N, 0.15, 20 + i, 30 + i, d)
+        ms.append(m), refs.append(ref), bs.append(b), bhs.append(bh)
+    lams = [1.0, 0.5, 1.0, 2.0]
+    xs = [torch.empty_like(b) for b in bs]
+    st, res = hb.batch_solve(ms, lams, bs, xs, max_iter=5000, rtol=1e-10, precond=hb.PRECOND_JACOBI, graph_k=graph_k)
+    assert st == hb.HB_OK, [r.status for r in res]
+    for i in range(len(shapes)):
+        o = refs[i].pcg(bhs[i], lams[i], max_iter=5000, rtol=1e-10)
+        tr = np.linalg.norm(bhs[i] - refs[i].ax(host(xs[i]), lams[i])) / np.linalg.norm(bhs[i])
+        say(f"  problem {i}: {res[i].iters} iterations (oracle {o['iters']}), true residual {tr:.2e}")
+        assert abs(res[i].iters - o["iters"]) <= 2 and tr <= 1.2e-10
+        assert res[i].res0 == pytest.approx(np.linalg.norm(bhs[i]), rel=1e-13)
+        assert res[i].res <= 1e-10 * res[i].bnorm
+    xs = [torch.empty_like(b) for b in bs]
+    st, res = hb.batch_solve(ms, lams, bs, xs, max_iter=40, fixed_iters=True, precond=hb.PRECOND_JACOBI,
+                             graph_k=graph_k)
+    assert st == hb.HB_OK and all(r.iters == 40 for r in res)
+    for i, m in enumerate(ms):
+        x1 = torch.empty_like(bs[i])
+        m.cg(lams[i], bs[i], x1, max_iter=40, fixed_iters=True, precond=hb.PRECOND_JACOBI)
+        ex = relerr(host(xs[i]), host(x1))
+        xo = refs[i].pcg(bhs[i], lams[i], fixed_iters=40)["x"]
+        eo = relerr(host(xs[i]), xo)
+        say(f"  problem {i}: 40 iterations vs one-problem {ex:.2e}, vs oracle {eo:.2e}")
+        assert ex <= 1e-9 and eo <= 1e-9
+    for m in ms:
+        m.close()

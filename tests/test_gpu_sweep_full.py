@@ -2,7 +2,8 @@
 jittered, in the launch configuration the sweep measures (default tile
 schedules).  Every output of the FP64 operator is compared with the oracle
 (1e-12 relative), and the FP32 operator with the same derived bar as the
-small cases (parity unpinned: no FP32 reference exists)."""
+small cases (parity unpinned: no FP32 reference exists); the two-phase operator
+(HB_MESH_GATHER) on the same mesh and input to the FP64 bar."""
 import sys
 
 import numpy as np
@@ -43,7 +44,14 @@ def test_order_sweep_full_size(N):
     torch.cuda.synchronize()
     e64 = relerr(y.cpu().numpy(), yref)
     e32 = relerr(y32.cpu().numpy().astype(np.float64), yref)
-    print(f"N={N}: FP64 {e64:.2e}, FP32 {e32:.2e}", flush=True)
-    assert e64 <= 1e-12
-    assert 1e-9 < e32 <= 2e-5
     m.close()
+    del y32
+    g = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, gather=True)
+    yg = torch.empty_like(xd)
+    g.ax(c.lam, xd, yg)
+    torch.cuda.synchronize()
+    eg = relerr(yg.cpu().numpy(), yref)
+    g.close()
+    print(f"N={N}: FP64 {e64:.2e}, FP32 {e32:.2e}, two-phase {eg:.2e}", flush=True)
+    assert e64 <= 1e-12 and eg <= 1e-12
+    assert 1e-9 < e32 <= 2e-5
