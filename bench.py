@@ -253,8 +253,9 @@ def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
 
 def served_vs_sequential(hb, torch, inputs, count, rtol=1e-8):
     """The first `count` arrivals of the serving trace through the engine (FP32
-    operator with FP64 residual replacement, 64 GB budget) and one at a time
-    with FP64 CG; solves/s and latency percentiles."""
+    operator with FP64 residual replacement, and FP64 with the Jacobi
+    preconditioner; 64 GB budget) and one at a time with FP64 CG; solves/s and
+    latency percentiles."""
     from paper_2202_12477_amd import serving
 
     trace = inputs.serving_trace(count)
@@ -262,6 +263,9 @@ def served_vs_sequential(hb, torch, inputs, count, rtol=1e-8):
            "trace_s": round(trace[-1][0], 3), "hbm_budget_gb": 64}
     out["engine_fp32rr"] = serving.replay_engine(trace, prec=hb.PREC_FP32_RR, rtol=rtol, progress=16)
     print(f"# serving engine: {out['engine_fp32rr']}", file=sys.stderr, flush=True)
+    out["engine_fp64_jacobi"] = serving.replay_engine(trace, prec=hb.PREC_FP64, rtol=rtol,
+                                                      precond=hb.PRECOND_JACOBI, progress=16)
+    print(f"# serving engine (FP64, Jacobi): {out['engine_fp64_jacobi']}", file=sys.stderr, flush=True)
     out["sequential_fp64"] = serving.replay_sequential(trace, rtol=rtol, progress=16)
     print(f"# serving sequential: {out['sequential_fp64']}", file=sys.stderr, flush=True)
     return out

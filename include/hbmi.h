@@ -63,6 +63,7 @@ enum {
                              [0,1]^3 carry no DOF, so N_G = (nx N - 1)(ny N - 1)(nz N - 1), numbered
                              lexicographically over the interior nodes; needs nx N, ny N, nz N >= 2 */
     HB_MESH_GATHER = 4    /* two-phase operator (the Poisson Operator section's own form): the element kernel
+                             (under the degree's default FP64 tile schedule; the schedule table does not apply)
                              writes the local vector y_L (8 N_L bytes kept with the mesh), then a gather sums
                              each DOF's local copies in ascending local order (Z^T as CSR rows, 4 (N_G + 1)
                              + 4 N_L bytes, built at creation from the map on the host).  Every hb_ax, hb_ax_add
@@ -274,6 +275,8 @@ typedef struct {
                                capped at max_quota (<= 0: 64; 1: every request advances equally) */
     int32_t graphs;         /* 1: a step's launches are replays of a captured HIP graph, re-captured whenever
                                the set of running requests (or the step length) changes; 0: plain launches */
+    int32_t precond;        /* hb_precond: HB_PRECOND_JACOBI (with HB_PREC_FP64 only) solves every request with
+                               the Jacobi preconditioner, its 1 / diag(A) (8 N_G bytes) part of the footprint */
 } hb_engine_opts;
 
 typedef struct {
@@ -284,7 +287,8 @@ typedef struct {
     size_t used_bytes;      /* footprint of the admitted requests */
 } hb_engine_info;
 
-/* Device bytes a request holds while admitted (pure host arithmetic). */
+/* Device bytes a request holds while admitted (pure host arithmetic), without a
+ * preconditioner (an engine with HB_PRECOND_JACOBI adds 8 N_G). */
 hb_status hb_engine_footprint(const hb_mesh_desc *desc, int32_t prec, int32_t max_iter, size_t *bytes);
 hb_status hb_engine_create(const hb_engine_opts *opts, void *stream, hb_engine *out);
 /* Releases every device buffer (admitted requests are dropped).  NULL is accepted. */

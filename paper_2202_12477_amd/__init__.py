@@ -65,7 +65,7 @@ class _MeshInfo(ctypes.Structure):
 class _EngineOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("iters_per_step", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("max_quota", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("max_quota", ctypes.c_int32), ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class _EngineInfo(ctypes.Structure):
@@ -333,8 +333,9 @@ class Engine:
 
     def __init__(self, hbm_budget: int, max_slots: int, prec: int = PREC_FP32_RR, max_iter: int = 100000,
                  iters_per_step: int = 25, inner_rtol: float = 0.0, max_quota: int = 0, graphs: bool = False,
-                 stream=None):
-        o = _EngineOpts(hbm_budget, max_slots, prec, max_iter, iters_per_step, inner_rtol, max_quota, int(graphs))
+                 precond: int = PRECOND_NONE, stream=None):
+        o = _EngineOpts(hbm_budget, max_slots, prec, max_iter, iters_per_step, inner_rtol, max_quota, int(graphs),
+                        precond)
         h = ctypes.c_void_p()
         self._stream = _stream(stream)
         _check(lib().hb_engine_create(ctypes.byref(o), self._stream, ctypes.byref(h)), "hb_engine_create")

@@ -481,7 +481,7 @@ class BatchRunner {
 
 // Device bytes one request holds while it is admitted (mesh, FP32 copy,
 // CG workspace, b and x, histories).
-size_t request_footprint(const hb_mesh_desc &d, int prec, int max_iter)
+size_t request_footprint(const hb_mesh_desc &d, int prec, int max_iter, bool jacobi)
 {
     const double n1 = d.N + 1.0;
     const double NL = (double)d.nx * d.ny * d.nz * n1 * n1 * n1;
@@ -490,6 +490,7 @@ size_t request_footprint(const hb_mesh_desc &d, int prec, int max_iter)
     double bytes = NL * (4.0 + 8.0 * kGeo) + (mixed ? NL * 4.0 * kGeo : 0.0);  // map, geometry
     bytes += NG * (8.0 * 3 + (mixed ? 4.0 : 0.0));                               // r, p, Ap (+ FP32 Ap)
     bytes += NG * 16.0;                                                          // b, x
+    if (jacobi) bytes += NG * 8.0;                                               // 1 / diag(A)
     bytes += 16.0 * (max_iter + 1.0) + 8.0 * (NL / 16.0 + NG / 512.0) + 4096.0;  // histories, partials, small
     return static_cast<size_t>(bytes);
 }
@@ -595,7 +596,7 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
 hb_status hb_engine_footprint(const hb_mesh_desc *desc, int32_t prec, int32_t max_iter, size_t *bytes)
 {
     if (!desc || !bytes || max_iter < 0) return fail(HB_ERR_INVALID_ARG, "hb_engine_footprint: bad arguments");
-    *bytes = request_footprint(*desc, prec, max_iter);
+    *bytes = request_footprint(*desc, prec, max_iter, false);
     return HB_OK;
 }
 
@@ -604,8 +605,11 @@ hb_status hb_engine_create(const hb_engine_opts *opts, void *stream, hb_engine *
     if (out) *out = nullptr;
     if (!opts || !out) return fail(HB_ERR_INVALID_ARG, "hb_engine_create: null argument");
     if (opts->max_slots < 1 || opts->hbm_budget == 0 || opts->max_iter < 1 ||
-        (opts->prec != HB_PREC_FP64 && opts->prec != HB_PREC_FP32_RR))
+        (opts->prec != HB_PREC_FP64 && opts->prec != HB_PREC_FP32_RR) ||
+        (opts->precond != HB_PRECOND_NONE && opts->precond != HB_PRECOND_JACOBI))
         return fail(HB_ERR_INVALID_ARG, "hb_engine_create: bad options");
+    if (opts->precond == HB_PRECOND_JACOBI && opts->prec != HB_PREC_FP64)
+        return fail(HB_ERR_INVALID_ARG, "hb_engine_create: the Jacobi preconditioner is available with HB_PREC_FP64 only");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
         (void)hipGetLastError();
@@ -651,7 +655,7 @@ hb_status hb_engine_submit(hb_engine e, const hb_mesh_desc *desc, double lambda,
         return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: a Dirichlet box needs interior nodes (n*N >= 2)");
     if (!(lambda > 0.0) || !std::isfinite(lambda) || !(rtol > 0.0))
         return fail(HB_ERR_INVALID_ARG, "hb_engine_submit: lambda and rtol must be > 0");
-    const size_t fp = request_footprint(*desc, e->opts.prec, e->opts.max_iter);
+    const size_t fp = request_footprint(*desc, e->opts.prec, e->opts.max_iter, e->opts.precond == HB_PRECOND_JACOBI);
     if (fp > e->opts.hbm_budget)
         return fail(HB_ERR_BUDGET, "hb_engine_submit: the request needs " + std::to_string(fp) +
                                        " device bytes, more than the whole budget");
@@ -693,6 +697,7 @@ hb_status hb_engine_step(hb_engine e, int32_t iters, hb_engine_info *info)
         o.x0_zero = 1;
         o.prec = e->opts.prec;
         o.inner_rtol = e->opts.inner_rtol;
+        o.precond = e->opts.precond;
         if ((st = e->runner->add(slot, a.mesh, r.lambda, a.b, a.x, o))) {
             e->release(a);
             return st;

@@ -30,12 +30,13 @@ def _summary(lat, wall, iters, extra=None):
 
 
 def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, iters_per_step=25,
-                  max_iter=200000, progress=None):
+                  max_iter=200000, precond=0, progress=None):
     """Submit each request when its arrival time has passed, step the engine while
     anything is queued or running, and poll for completions after every step."""
     import torch
 
-    eng = Engine(hbm_budget, max_slots=max_slots, prec=prec, max_iter=max_iter, iters_per_step=iters_per_step)
+    eng = Engine(hbm_budget, max_slots=max_slots, prec=prec, max_iter=max_iter, iters_per_step=iters_per_step,
+                 precond=precond)
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -186,3 +186,34 @@ def test_batched_pcg(graph_k):
         assert ex <= 1e-9 and eo <= 1e-9
     for m in ms:
         m.close()
+
+
+def test_engine_pcg():
+    """The serving engine with the Jacobi preconditioner (FP64): every request
+    reaches its tolerance on the true residual in the oracle's PCG iteration
+    count (+-2)."""
+    say("[case] engine PCG")
+    reqs = [(3, 3, 2, 5, False, 41), (2, 2, 3, 7, True, 42), (4, 3, 3, 3, True, 43)]
+    eng = hb.Engine(1 << 30, max_slots=2, prec=hb.PREC_FP64, iters_per_step=15, precond=hb.PRECOND_JACOBI)
+    tickets = {eng.submit(nx, ny, nz, N, jitter=0.15, seed=s, rhs_seed=s + 100, rtol=1e-10, dirichlet=d): i
+               for i, (nx, ny, nz, N, d, s) in enumerate(reqs)}
+    got = {}
+    for _ in range(100000):
+        if len(got) == len(reqs):
+            break
+        eng.step()
+        for t, i in tickets.items():
+            if i not in got:
+                out = eng.poll(t)
+                if out is not None:
+                    got[i] = out
+    eng.close()
+    assert len(got) == len(reqs)
+    for i, (nx, ny, nz, N, d, s) in enumerate(reqs):
+        ref = oracle.Mesh(nx, ny, nz, N, jitter=0.15, seed=s, dirichlet=d)
+        bh = oracle.rhs(ref.NG, s + 100)
+        res, x = got[i]
+        o = ref.pcg(bh, 1.0, max_iter=5000, rtol=1e-10)
+        tr = np.linalg.norm(bh - ref.ax(x, 1.0)) / np.linalg.norm(bh)
+        say(f"  request {i}: {res.iters} iterations (oracle {o['iters']}), true residual {tr:.2e}")
+        assert res.status == hb.HB_OK and abs(res.iters - o["iters"]) <= 2 and tr <= 1.2e-10
