@@ -208,8 +208,8 @@ def two_phase_vs_fused(hb, torch, metrics, B, n, N, dirichlet, label):
 def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
     """The 64 uneven problems: one-by-one FP64 CG vs the batched solver (FP64, FP64
     with the Jacobi preconditioner, and FP32 operator with FP64 residual
-    replacement with plain launches and with 25-iteration segments replayed from
-    captured graphs), all to rtol; solves/s."""
+    replacement without and with Jacobi, and with 25-iteration segments replayed
+    from captured graphs), all to rtol; solves/s."""
     cases = inputs.batched_cases()
     meshes, bs = [], []
     for c in cases:
@@ -238,6 +238,7 @@ def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
     for name, fn in (("sequential_fp64", seq), ("batched_fp64", lambda: batch(hb.PREC_FP64)),
                      ("batched_fp64_jacobi", lambda: batch(hb.PREC_FP64, precond=hb.PRECOND_JACOBI)),
                      ("batched_fp32rr", lambda: batch(hb.PREC_FP32_RR)),
+                     ("batched_fp32rr_jacobi", lambda: batch(hb.PREC_FP32_RR, precond=hb.PRECOND_JACOBI)),
                      ("batched_fp32rr_graphs", lambda: batch(hb.PREC_FP32_RR, graph_k=25))):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -253,9 +254,9 @@ def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
 
 def served_vs_sequential(hb, torch, inputs, count, rtol=1e-8):
     """The first `count` arrivals of the serving trace through the engine (FP32
-    operator with FP64 residual replacement, and FP64 with the Jacobi
-    preconditioner; 64 GB budget) and one at a time with FP64 CG; solves/s and
-    latency percentiles."""
+    operator with FP64 residual replacement; FP64 and FP32 with residual
+    replacement, both with the Jacobi preconditioner; 64 GB budget) and one at a
+    time with FP64 CG; solves/s and latency percentiles."""
     from paper_2202_12477_amd import serving
 
     trace = inputs.serving_trace(count)
@@ -263,9 +264,9 @@ def served_vs_sequential(hb, torch, inputs, count, rtol=1e-8):
            "trace_s": round(trace[-1][0], 3), "hbm_budget_gb": 64}
     out["engine_fp32rr"] = serving.replay_engine(trace, prec=hb.PREC_FP32_RR, rtol=rtol, progress=16)
     print(f"# serving engine: {out['engine_fp32rr']}", file=sys.stderr, flush=True)
-    out["engine_fp64_jacobi"] = serving.replay_engine(trace, prec=hb.PREC_FP64, rtol=rtol,
-                                                      precond=hb.PRECOND_JACOBI, progress=16)
-    print(f"# serving engine (FP64, Jacobi): {out['engine_fp64_jacobi']}", file=sys.stderr, flush=True)
+    for name, prec in (("engine_fp64_jacobi", hb.PREC_FP64), ("engine_fp32rr_jacobi", hb.PREC_FP32_RR)):
+        out[name] = serving.replay_engine(trace, prec=prec, rtol=rtol, precond=hb.PRECOND_JACOBI, progress=16)
+        print(f"# serving {name}: {out[name]}", file=sys.stderr, flush=True)
     out["sequential_fp64"] = serving.replay_sequential(trace, rtol=rtol, progress=16)
     print(f"# serving sequential: {out['sequential_fp64']}", file=sys.stderr, flush=True)
     return out

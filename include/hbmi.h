@@ -187,8 +187,8 @@ typedef struct {
                             hb_batch_solve: > 0 makes each segment graph_k iterations long (instead of
                             check_every) and replays it from a captured graph until the set of running
                             problems changes. At most 4096. */
-    int32_t precond;     /* hb_precond; HB_PRECOND_JACOBI with HB_PREC_FP64 only (hb_cg_solve and hb_batch_solve;
-                            the engine runs unpreconditioned CG) */
+    int32_t precond;     /* hb_precond; HB_PRECOND_JACOBI with HB_PREC_FP64 or HB_PREC_FP32_RR (each residual
+                            replacement then also recomputes r.z), not with HB_PREC_FP32_IR */
 } hb_cg_opts;
 
 typedef struct {
@@ -275,8 +275,9 @@ typedef struct {
                                capped at max_quota (<= 0: 64; 1: every request advances equally) */
     int32_t graphs;         /* 1: a step's launches are replays of a captured HIP graph, re-captured whenever
                                the set of running requests (or the step length) changes; 0: plain launches */
-    int32_t precond;        /* hb_precond: HB_PRECOND_JACOBI (with HB_PREC_FP64 only) solves every request with
-                               the Jacobi preconditioner, its 1 / diag(A) (8 N_G bytes) part of the footprint */
+    int32_t precond;        /* hb_precond: HB_PRECOND_JACOBI solves every request with the Jacobi
+                               preconditioner (either precision), its 1 / diag(A) (8 N_G bytes) part of the
+                               footprint */
 } hb_engine_opts;
 
 typedef struct {

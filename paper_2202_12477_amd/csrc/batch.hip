@@ -51,23 +51,21 @@ __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkI
     const int64_t hi = lo + kBatchChunk < NG ? lo + kBatchChunk : NG;
     const auto r = to_global(uniform(P.r));
     double rr = 0.0;
-    if (uniform(P.use32)) {
-        const auto Ap = to_global(uniform(P.Ap32));
-        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const double ri = r[i] - alpha * static_cast<double>(Ap[i]);
-            r[i] = ri;
-            rr += ri * ri;
-        }
-    } else if (uniform(P.inv)) {
-        const auto Ap = to_global(uniform(P.Ap));
+    if (uniform(P.inv)) {
         const auto inv = to_global(uniform(P.inv));
         double rz = 0.0;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const double ri = r[i] - alpha * Ap[i];
-            r[i] = ri;
-            rr += ri * ri;
-            rz += ri * (inv[i] * ri);
-        }
+        auto sweep = [&](auto Ap) {
+            for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+                const double ri = r[i] - alpha * static_cast<double>(Ap[i]);
+                r[i] = ri;
+                rr += ri * ri;
+                rz += ri * (inv[i] * ri);
+            }
+        };
+        if (uniform(P.use32))
+            sweep(to_global(uniform(P.Ap32)));
+        else
+            sweep(to_global(uniform(P.Ap)));
         rr = block_sum(rr, red);
         rz = block_sum(rz, red);
         if (threadIdx.x == 0) {
@@ -75,6 +73,14 @@ __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkI
             to_global(uniform(P.part_vec))[uniform(P.vec_chunks) + chunk] = rr;
         }
         return;
+    }
+    if (uniform(P.use32)) {
+        const auto Ap = to_global(uniform(P.Ap32));
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const double ri = r[i] - alpha * static_cast<double>(Ap[i]);
+            r[i] = ri;
+            rr += ri * ri;
+        }
     } else {
         const auto Ap = to_global(uniform(P.Ap));
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {

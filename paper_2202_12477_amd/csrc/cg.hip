@@ -209,33 +209,41 @@ __global__ __launch_bounds__(kVecThreads) void invert_kernel(int64_t n, double *
         v[i] = 1.0 / v[i];
 }
 
-// r = b - t; partials of r.r.
+// r = b - t; partials of r.r (and, with inv, of r.z, z = inv r, after them).
 __global__ __launch_bounds__(kVecThreads) void residual_norm_kernel(int64_t n, const double *__restrict__ b,
                                                                    const double *__restrict__ t,
                                                                    double *__restrict__ r,
+                                                                   const double *__restrict__ inv,
                                                                    double *__restrict__ partial)
 {
     __shared__ double red[kVecThreads / 64];
-    double rr = 0.0;
+    double rr = 0.0, rz = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double ri = b[i] - t[i];
         r[i] = ri;
         rr += ri * ri;
+        if (inv) rz += ri * (inv[i] * ri);
     }
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = rr;
+    if (inv) {
+        rz = block_sum(rz, red);
+        if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = rz;
+    }
 }
 
+// rho_iters = r.r (Jacobi, pc: r.z), history entry iters = ||r||, *out = r.r.
 __global__ __launch_bounds__(kFinThreads) void replace_finish_kernel(const double *__restrict__ partial, int nblk,
-                                                                    CgState *st, double *__restrict__ rho,
+                                                                    int pc, CgState *st, double *__restrict__ rho,
                                                                     double *__restrict__ hist,
                                                                     double *__restrict__ out)
 {
     __shared__ double red[kFinThreads / 64];
     const double rr = sum_partials(partial, nblk, red);
+    const double rz = pc ? sum_partials(partial + nblk, nblk, red) : rr;
     if (threadIdx.x != 0) return;
     const int j = st->iters;
-    rho[j] = rr;
+    rho[j] = rz;
     hist[j] = sqrt(rr);
     *out = rr;
 }
@@ -377,18 +385,18 @@ hb_status launch_residual_norm(int64_t n, const double *b, const double *t, doub
                                hipStream_t s)
 {
     const int g = vec_blocks(n);
-    residual_norm_kernel<<<g, kVecThreads, 0, s>>>(n, b, t, r, w.part_vec);
+    residual_norm_kernel<<<g, kVecThreads, 0, s>>>(n, b, t, r, nullptr, w.part_vec);
     sum_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, out);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
 
 hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st,
-                            double *out, hipStream_t s)
+                            double *out, const double *inv, hipStream_t s)
 {
     const int g = vec_blocks(n);
-    residual_norm_kernel<<<g, kVecThreads, 0, s>>>(n, b, t, r, w.part_vec);
-    replace_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, st, w.rho, w.hist, out);
+    residual_norm_kernel<<<g, kVecThreads, 0, s>>>(n, b, t, r, inv, w.part_vec);
+    replace_finish_kernel<<<1, kFinThreads, 0, s>>>(w.part_vec, g, inv ? 1 : 0, st, w.rho, w.hist, out);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }

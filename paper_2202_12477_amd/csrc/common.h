@@ -220,10 +220,11 @@ hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp
 // 1 / diag(A) into inv (Jacobi preconditioner), for the mesh's operator at lambda.
 hb_status launch_jacobi_inverse(const hb_mesh_s *m, double lambda, double *inv, hipStream_t s);
 // Residual replacement after the completed iterations: r = b - t (t = A x
-// from the FP64 operator), rho_iters = r.r, history entry iters, *out = r.r;
-// then the solve resumes with a new stopping threshold on ||r||.
+// from the FP64 operator), rho_iters = r.r (r.z with the Jacobi inverse
+// diagonal inv), history entry iters = ||r||, *out = r.r; then the solve
+// resumes with a new stopping threshold on ||r||.
 hb_status launch_cg_replace(int64_t n, const double *b, const double *t, double *r, CgWork &w, CgState *st,
-                            double *out, hipStream_t s);
+                            double *out, const double *inv, hipStream_t s);
 hb_status launch_cg_resume(CgState *st, double stop_res, hipStream_t s);
 // Refinement helpers: r = b - t with ||r||^2 into *out (one block finishes), and x += d.
 hb_status launch_residual_norm(int64_t n, const double *b, const double *t, double *r, CgWork &w, double *out,

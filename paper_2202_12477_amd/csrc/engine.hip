@@ -106,9 +106,9 @@ class BatchRunner {
         st = cg_start(m, lambda, b, x, states_ + i, o.x0_zero, o.max_iter, rtol, mixed, s_);
         m->cg.pc = false;
         if (st) return st;
-        // mixed: r0.r0 (the replacement's start); FP64: ||r0|| from the residual
-        // history (r0.r0 is not kept when the iteration is preconditioned)
-        HB_HIP(hipMemcpyAsync(h_rho_ + i, mixed ? m->cg.rho : m->cg.hist, sizeof(double), hipMemcpyDeviceToHost, s_));
+        // ||r0|| from the residual history (r0.r0 is not kept when the iteration
+        // is preconditioned)
+        HB_HIP(hipMemcpyAsync(h_rho_ + i, m->cg.hist, sizeof(double), hipMemcpyDeviceToHost, s_));
         CgWork &w = m->cg;
         BatchProb &P = h_probs_[i];
         P.map = m->map;
@@ -138,6 +138,7 @@ class BatchRunner {
         P.vec_chunks = static_cast<int32_t>((m->NG + kBatchChunk - 1) / kBatchChunk);
         P.use32 = mixed ? 1 : 0;
         P.inv = pc ? w.jinv : nullptr;
+        q.rp.inv = P.inv;
         dirty_ = true;
         return HB_OK;
     }
@@ -281,7 +282,7 @@ class BatchRunner {
             q.starting = false;
             const CgState &hs = h_states_[i];
             if (q.mixed) {
-                q.rp.start(&q.opts, std::sqrt(h_rho_[i]), std::sqrt(hs.bb), hs.done != 0,
+                q.rp.start(&q.opts, h_rho_[i], std::sqrt(hs.bb), hs.done != 0,
                            static_cast<hb_status>(hs.status));
                 if (q.rp.finished) {
                     finish(i, hs.iters);
@@ -555,8 +556,9 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
         return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: graph_k must be in [0, 4096]");
     if (opts->precond != HB_PRECOND_NONE && opts->precond != HB_PRECOND_JACOBI)
         return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: unknown preconditioner");
-    if (opts->precond == HB_PRECOND_JACOBI && opts->prec != HB_PREC_FP64)
-        return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: the Jacobi preconditioner is available with HB_PREC_FP64 only");
+    if (opts->precond == HB_PRECOND_JACOBI && opts->prec == HB_PREC_FP32_IR)
+        return fail(HB_ERR_INVALID_ARG,
+                    "hb_batch_solve: the Jacobi preconditioner is available with HB_PREC_FP64 and HB_PREC_FP32_RR only");
     for (int i = 0; i < nprob; ++i) {
         if (!meshes[i] || !dev_b[i] || !dev_x[i] || dev_b[i] == dev_x[i])
             return fail(HB_ERR_INVALID_ARG, "hb_batch_solve: problem " + std::to_string(i) + ": bad pointers");
@@ -608,8 +610,7 @@ hb_status hb_engine_create(const hb_engine_opts *opts, void *stream, hb_engine *
         (opts->prec != HB_PREC_FP64 && opts->prec != HB_PREC_FP32_RR) ||
         (opts->precond != HB_PRECOND_NONE && opts->precond != HB_PRECOND_JACOBI))
         return fail(HB_ERR_INVALID_ARG, "hb_engine_create: bad options");
-    if (opts->precond == HB_PRECOND_JACOBI && opts->prec != HB_PREC_FP64)
-        return fail(HB_ERR_INVALID_ARG, "hb_engine_create: the Jacobi preconditioner is available with HB_PREC_FP64 only");
+
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
         (void)hipGetLastError();

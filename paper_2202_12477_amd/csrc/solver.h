@@ -43,6 +43,7 @@ struct Replacer {
     double eta = 1e-3, rtol = 0.0, bnorm = 0.0, ref = 0.0, res = 0.0, res0 = 0.0;
     int max_iter = 0, max_outer = 0, outer = 0, fp64_from = -1;
     bool use32 = true, finished = false, breakdown = false;
+    const double *inv = nullptr;  // Jacobi: 1 / diag(A) (the replacement then also recomputes r.z)
     hb_status status = HB_ERR_NOT_CONVERGED;
 
     void start(const hb_cg_opts *o, double res0_, double bnorm_, bool already_done, hb_status st0)
@@ -74,7 +75,7 @@ struct Replacer {
         CgWork &w = m->cg;
         hb_status e;
         if ((e = launch_zero(w.Ap, m->NG, s)) || (e = launch_ax(m, lambda, x, w.Ap, nullptr, nullptr, s)) ||
-            (e = launch_cg_replace(m->NG, b, w.Ap, w.r, w, st, norm_out, s)))
+            (e = launch_cg_replace(m->NG, b, w.Ap, w.r, w, st, norm_out, inv, s)))
             return e;
         *enqueued = true;
         return HB_OK;

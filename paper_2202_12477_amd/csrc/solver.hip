@@ -279,10 +279,11 @@ hb_status solve_replace(hb_mesh_s *m, double lambda, const double *b, double *x,
     if ((st = cg_start(m, lambda, b, x, w.state, opts->x0_zero, opts->max_iter, opts->rtol, true, s)) ||
         (st = read_state(w, s)))
         return st;
-    double rho0 = 0.0;
-    HB_HIP(hipMemcpy(&rho0, w.rho, sizeof(double), hipMemcpyDeviceToHost));
+    double res0 = 0.0;  // ||r0|| (the first history entry, also when preconditioned)
+    HB_HIP(hipMemcpy(&res0, w.hist, sizeof(double), hipMemcpyDeviceToHost));
     Replacer rp;
-    rp.start(opts, std::sqrt(rho0), std::sqrt(w.host_state->bb), w.host_state->done != 0,
+    rp.inv = w.pc ? w.jinv : nullptr;
+    rp.start(opts, res0, std::sqrt(w.host_state->bb), w.host_state->done != 0,
              static_cast<hb_status>(w.host_state->status));
     if (hist && opts->max_iter >= 0) hist[0] = rp.res0;
     if (!rp.finished && (st = launch_cg_resume(w.state, rp.threshold(), s))) return st;

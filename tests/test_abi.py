@@ -113,7 +113,7 @@ def test_engine_needs_device(L):
     assert L.hb_engine_destroy(None) == hb.HB_OK
     bad = hb._EngineOpts(1 << 30, 0, hb.PREC_FP64, 100, 25, 0.0)
     assert L.hb_engine_create(ctypes.byref(bad), None, ctypes.byref(h)) == hb.HB_ERR_INVALID_ARG
-    for prec, precond in ((hb.PREC_FP64, 2), (hb.PREC_FP32_RR, hb.PRECOND_JACOBI)):
+    for prec, precond in ((hb.PREC_FP64, 2), (hb.PREC_FP32_RR, -1)):
         bad = hb._EngineOpts(1 << 30, 4, prec, 100, 25, 0.0, 0, 0, precond)
         assert L.hb_engine_create(ctypes.byref(bad), None, ctypes.byref(h)) == hb.HB_ERR_INVALID_ARG
 
