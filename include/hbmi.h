@@ -187,8 +187,9 @@ typedef struct {
                             hb_batch_solve: > 0 makes each segment graph_k iterations long (instead of
                             check_every) and replays it from a captured graph until the set of running
                             problems changes. At most 4096. */
-    int32_t precond;     /* hb_precond; HB_PRECOND_JACOBI with HB_PREC_FP64 or HB_PREC_FP32_RR (each residual
-                            replacement then also recomputes r.z), not with HB_PREC_FP32_IR */
+    int32_t precond;     /* hb_precond: HB_PRECOND_JACOBI in every precision (HB_PREC_FP32_RR: each residual
+                            replacement also recomputes r.z; HB_PREC_FP32_IR: the inner FP32 solves and the
+                            FP64 fallback are preconditioned); hb_batch_solve: not with HB_PREC_FP32_IR */
 } hb_cg_opts;
 
 typedef struct {

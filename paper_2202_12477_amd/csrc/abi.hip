@@ -256,9 +256,6 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
         return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: mixed precision needs a mesh built with HB_MESH_FP32");
     if (opts->precond != HB_PRECOND_NONE && opts->precond != HB_PRECOND_JACOBI)
         return fail(HB_ERR_INVALID_ARG, "hb_cg_solve: unknown preconditioner");
-    if (opts->precond == HB_PRECOND_JACOBI && opts->prec == HB_PREC_FP32_IR)
-        return fail(HB_ERR_INVALID_ARG,
-                    "hb_cg_solve: the Jacobi preconditioner is available with HB_PREC_FP64 and HB_PREC_FP32_RR only");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hb_status st = ensure_cg(m, opts->max_iter, mixed, opts->prec == HB_PREC_FP32_IR);
     if (st) return st;
@@ -266,17 +263,17 @@ hb_status hb_cg_solve(hb_mesh m, double lambda, const double *dev_b, double *dev
     w.graph_k = opts->graph_k;
     const bool pc = opts->precond == HB_PRECOND_JACOBI;
     if (pc && (st = ensure_jacobi(m, lambda, s))) return st;
-    if (opts->prec == HB_PREC_FP32_RR) {
-        w.pc = pc;
-        st = solve_replace(m, lambda, dev_b, dev_x, opts, result, host_res_hist, s);
-        w.pc = false;
-        return st;
-    }
+    // every CG iteration of this solve (inner solves of the refinement included)
+    // is preconditioned; the flag is cleared on every way out
+    struct PcScope {
+        CgWork &w;
+        PcScope(CgWork &w_, bool on) : w(w_) { w.pc = on; }
+        ~PcScope() { w.pc = false; }
+    } pc_scope(w, pc);
+    if (opts->prec == HB_PREC_FP32_RR) return solve_replace(m, lambda, dev_b, dev_x, opts, result, host_res_hist, s);
     if (!mixed) {
-        w.pc = pc;
         st = run_cg<double>(m, lambda, dev_b, dev_x, w.Ap, opts->x0_zero, opts->max_iter,
                             opts->fixed_iters ? -1.0 : opts->rtol, opts->check_every, s);
-        w.pc = false;
         if (st) return st;
         const CgState hs = *w.host_state;
         // ||r_0|| and ||r_iters|| (hist holds the residual norms in both forms of the iteration)
