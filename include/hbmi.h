@@ -7,8 +7,9 @@
  * the screened Poisson operator A = S + lambda*(mass) of eq. (poisson), with the
  * stiffness S = Z^T S_L Z of eq. (stiffness), S_L^e = D^T G^e D, applied
  * matrix-free to an *assembled* DOF vector (DOF Storage section), inside
- * Algorithm 1 (unpreconditioned CG) with fused vector kernels (Conjugate
- * gradient Iteration section).
+ * Algorithm 1 (unpreconditioned CG; optionally with a Jacobi
+ * preconditioner) with fused vector kernels (Conjugate gradient Iteration
+ * section).
  *
  * Conventions shared by every entry point:
  *  - Every function returns hb_status and never throws.  On failure a
