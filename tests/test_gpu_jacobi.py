@@ -185,13 +185,15 @@ def test_batched_pcg(graph_k):
         m.close()
 
 
-def test_engine_pcg():
-    """The serving engine with the Jacobi preconditioner (FP64): every request
-    reaches its tolerance on the true residual in the oracle's PCG iteration
-    count (+-2)."""
-    say("[case] engine PCG")
+@pytest.mark.parametrize("graphs", [False, True])
+def test_engine_pcg(graphs):
+    """The serving engine with the Jacobi preconditioner (FP64, plain launches and
+    graph replay of its steps): every request reaches its tolerance on the true
+    residual in the oracle's PCG iteration count (+-2)."""
+    say(f"[case] engine PCG graphs={graphs}")
     reqs = [(3, 3, 2, 5, False, 41), (2, 2, 3, 7, True, 42), (4, 3, 3, 3, True, 43)]
-    eng = hb.Engine(1 << 30, max_slots=2, prec=hb.PREC_FP64, iters_per_step=15, precond=hb.PRECOND_JACOBI)
+    eng = hb.Engine(1 << 30, max_slots=2, prec=hb.PREC_FP64, iters_per_step=15, precond=hb.PRECOND_JACOBI,
+                    graphs=graphs)
     tickets = {eng.submit(nx, ny, nz, N, jitter=0.15, seed=s, rhs_seed=s + 100, rtol=1e-10, dirichlet=d): i
                for i, (nx, ny, nz, N, d, s) in enumerate(reqs)}
     got = {}
