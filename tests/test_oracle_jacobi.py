@@ -2,7 +2,9 @@
 option, which the paper's benchmark leaves out): the assembled diagonal against
 the diagonal of the independently built dense matrix and against the Kronecker
 closed form of an affine box; the preconditioned iteration against a dense
-solve, and with M = I against the unpreconditioned oracle CG step for step."""
+solve, with M = I against the unpreconditioned oracle CG step for step, and
+with M = diag(A) against textbook CG on the symmetrically scaled system
+iterate by iterate."""
 import numpy as np
 import pytest
 
@@ -67,3 +69,37 @@ def test_jacobi_reduces_iterations_on_a_jittered_box():
     c = m.cg(b, 1.0, rtol=1e-8, max_iter=5000)
     assert p["status"] == c["status"] == 0
     assert p["iters"] < c["iters"]
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_pcg_is_cg_on_the_symmetrically_scaled_system(dirichlet):
+    """PCG with M = diag(A) = D is plain CG on D^-1/2 A D^-1/2 y = D^-1/2 b with
+    x = D^-1/2 y, and r = D^1/2 r_hat: each of the first 12 iterates and residual
+    norms of the oracle's PCG against a textbook dense CG on the scaled system
+    (the dense matrix built by the independent brute-force route)."""
+    n, N, lam = 2, 4, 0.8
+    m = Mesh(n, n, n, N, jitter=0.1, seed=17, dirichlet=dirichlet)
+    A = brute.dense_matrix(n, n, n, N, m.V, lam)
+    if dirichlet:
+        gx = n * N + 1
+        I, J, K = np.meshgrid(np.arange(1, gx - 1), np.arange(1, gx - 1), np.arange(1, gx - 1), indexing="ij")
+        keep = (I + gx * (J + gx * K)).ravel(order="F")
+        A = A[np.ix_(keep, keep)]
+    b = inputs.random_vector(m.NG, 21)
+    s = 1.0 / np.sqrt(np.diag(A))
+    Ah = s[:, None] * A * s[None, :]
+    bh = s * b
+    y, r = np.zeros_like(bh), bh.copy()
+    p, rr = r.copy(), r @ r
+    for k in range(1, 13):
+        Ap = Ah @ p
+        alpha = rr / (p @ Ap)
+        y = y + alpha * p
+        r = r - alpha * Ap
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        out = m.pcg(b, lam, fixed_iters=k)
+        x = s * y
+        assert np.linalg.norm(out["x"] - x) <= 1e-10 * np.linalg.norm(x), k
+        assert out["res"][k] == pytest.approx(np.linalg.norm(r / s), rel=1e-9), k
