@@ -10,6 +10,11 @@ by its known bytes, give the factor that turns the counters into HBM bytes for
 the operator's launches.
 
   python -m paper_2202_12477_amd.profile_ax [--case box32_N7_affine | sweepN] [--launches K] [--fp32 | --gather]
+      [--pcg K]
+
+--pcg K then also runs K fixed iterations of Jacobi-preconditioned FP64 CG on
+the same mesh (its vector kernels: residual_kernel<double, true>,
+update_kernel<double, true>).
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ def main():
     ap.add_argument("--launches", type=int, default=10)
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--gather", action="store_true")
+    ap.add_argument("--pcg", type=int, default=0)
     args = ap.parse_args()
     if args.fp32 and args.gather:
         ap.error("the two-phase operator is FP64 only")
@@ -55,8 +61,13 @@ def main():
         y = torch.zeros_like(b)
         for _ in range(args.launches):
             m.ax_add(c.lam, b, y)
+    if args.pcg > 0:
+        x = torch.empty_like(b)
+        r = m.cg(c.lam, b, x, max_iter=args.pcg, fixed_iters=True, history=False, precond=hb.PRECOND_JACOBI)
+        assert r.iters == args.pcg and r.status == hb.HB_OK, r
+        del x
     torch.cuda.synchronize()
-    print(f"operator {c.name} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={args.launches} "
+    print(f"operator {c.name} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={args.launches} pcg={args.pcg} "
           f"{'fp32' if args.fp32 else 'fp64'}{' two-phase' if args.gather else ''}", flush=True)
     m.close()
     del b, y
