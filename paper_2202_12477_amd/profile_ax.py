@@ -28,6 +28,8 @@ STREAM_N = 1 << 25
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--case", default="box32_N7_affine", help="box32_N7_affine, box4_N3_jitter or sweep<N>")
+    ap.add_argument("--dirichlet", action="store_true", help="the case's box with its boundary nodes masked")
+    ap.add_argument("--n", type=int, default=0, help="override the case's elements per edge (cubic box)")
     ap.add_argument("--launches", type=int, default=10)
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--gather", action="store_true")
@@ -46,7 +48,9 @@ def main():
         c = inputs.order_sweep_case(int(args.case[5:]))
     else:
         c = {k.name: k for k in (inputs.PLAIN_SMALL, inputs.PLAIN_LARGE)}[args.case]
-    m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=args.fp32, gather=args.gather)
+    nx, ny, nz = (args.n, args.n, args.n) if args.n > 0 else (c.nx, c.ny, c.nz)
+    m = hb.Mesh(nx, ny, nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=args.fp32, gather=args.gather,
+                dirichlet=args.dirichlet)
     b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
     hb.rhs_uniform(b, c.rhs_seed)
     if args.fp32:
@@ -67,7 +71,7 @@ def main():
         assert r.iters == args.pcg and r.status == hb.HB_OK, r
         del x
     torch.cuda.synchronize()
-    print(f"operator {c.name} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={args.launches} pcg={args.pcg} "
+    print(f"operator {c.name}{' dirichlet' if args.dirichlet else ''} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={args.launches} pcg={args.pcg} "
           f"{'fp32' if args.fp32 else 'fp64'}{' two-phase' if args.gather else ''}", flush=True)
     m.close()
     del b, y
