@@ -75,20 +75,74 @@ def stream_rate(hb, torch, n=1 << 25, reps=10):
     return 9 * 8 * n / statistics.median(times) / 1e9
 
 
-def cpu_baseline(case, reps=60):
-    """The oracle (plain C, single thread) timed on a bounded sample of the same workload."""
+def host_cpu():
+    """CPU model, logical CPUs of the host, and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, allowed
+
+
+def cpu_baseline(small, large, budget_s=8.0):
+    """The oracle (oracle/oracle.c, plain C FP64) timed on this host's cores: its
+    timing build (gcc -O3 -march=native -fopenmp, no FMA contraction; elements swept
+    in 8 classes that share no node, vector loops and dot products split over the
+    threads) on one thread and on every core this process may use (capped by
+    OMP_NUM_THREADS when set).  Each configuration is its benchmark unit: one
+    operator application plus 100 CG iterations from x0 = 0.  The one-thread run of
+    the 32^3 N=7 box does as many CG iterations as fit in about budget_s seconds
+    (a bounded sample, scaled per iteration); every other run is whole."""
+    import numpy as np
+
     import oracle
 
-    m = oracle.Mesh(case.nx, case.ny, case.nz, case.N, jitter=case.jitter, seed=case.mesh_seed)
-    b = oracle.rhs(m.NG, case.rhs_seed)
-    m.ax(b, case.lam)  # warm
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        m.ax(b, case.lam)
-    dt = time.perf_counter() - t0
-    return {"value": m.NG * reps / dt / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} operator applications y = A x on the same {case.nx}^3 N={case.N} mesh "
-                      f"({m.NG} DOFs), one thread, {dt:.1f} s"}
+    L = oracle.timing_lib(build=True)
+    model, nproc, allowed = host_cpu()
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(allowed, cap) if cap > 0 else allowed
+    out = {"cpu_model": model, "nproc": nproc, "cpus_allowed": allowed,
+           "build": " ".join(["gcc", *oracle.TIMING_CFLAGS]), "configs": {}}
+    for case in (small, large):
+        m = oracle.Mesh(case.nx, case.ny, case.nz, case.N, jitter=case.jitter, seed=case.mesh_seed)
+        b = oracle.rhs(m.NG, case.rhs_seed)
+        rec = {"n_global": m.NG}
+        for nt in sorted({1, threads}):
+            used = L.oracle_set_threads(nt)
+            t0 = time.perf_counter()
+            m.ax_classes(b, case.lam, L=L)
+            t_ax = time.perf_counter() - t0
+            iters = case.iters
+            if nt == 1 and case is large:
+                iters = max(2, min(case.iters, int(budget_s / max(t_ax * 1.3, 1e-9))))
+            t0 = time.perf_counter()
+            r = m.cg_classes(b, case.lam, fixed_iters=iters, L=L)
+            t_cg = time.perf_counter() - t0
+            assert r["iters"] == iters and np.all(np.isfinite(r["res"]))
+            rec[f"threads_{used}"] = {
+                "ax_s": round(t_ax, 4), "ax_gdofs": round(m.NG / t_ax / 1e9, 5),
+                "cg_iters_timed": iters, "cg_ms_per_iter": round(t_cg / iters * 1e3, 3),
+                "cg_gdofs": round(m.NG * iters / t_cg / 1e9, 5),
+                "unit_s": round(t_ax + t_cg / iters * case.iters, 3)}
+        out["configs"][case.name] = rec
+        del m, b
+    used = L.oracle_set_threads(threads)
+    best = out["configs"][large.name][f"threads_{used}"]
+    one = out["configs"][large.name]["threads_1"]
+    out.update({"value": best["ax_gdofs"], "unit": "GDOF/s", "cores": used, "kind": "oracle",
+                "sample": f"{large.name}: one y = A x ({large.NG} DOFs) on {used} threads "
+                          f"({best['ax_s']} s); beside it one thread ({one['ax_gdofs']} GDOF/s), and per "
+                          f"configuration one A x plus 100 CG iterations (one thread on {large.name}: "
+                          f"{one['cg_iters_timed']} iterations timed)"})
+    return out
 
 
 def paper_workload(hb, torch, metrics, B, n=50, N=7):
@@ -384,7 +438,7 @@ def main():
     if args.serve_requests > 0:
         out["serving"] = served_vs_sequential(hb, torch, inputs, args.serve_requests)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"] = cpu_baseline(inputs.PLAIN_SMALL, case)
     print(json.dumps(out), flush=True)
 
 

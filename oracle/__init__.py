@@ -35,7 +35,47 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+# The CPU baseline's timing build: the same source, optimised for the host it
+# runs on and multi-threaded with OpenMP (still no FMA contraction).  Built on
+# the machine that times it (-march=native), never used by the parity tests.
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+TIMING_CFLAGS = ["-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+                 "-std=c11", "-D_GNU_SOURCE"]
+
+
+def build_timing() -> str:
+    """Compile oracle.c into liboracle_omp.so (timing build) with gcc."""
+    tmp = _LIB_OMP + ".tmp"
+    subprocess.check_call(["gcc", *TIMING_CFLAGS, "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB_OMP)
+    return _LIB_OMP
+
+
 _lib = None
+_lib_omp = None
+
+
+def _declare(L: ctypes.CDLL) -> ctypes.CDLL:
+    dp = ctypes.POINTER(ctypes.c_double)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.oracle_ax_classes.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp, lp, lp, i32]
+    L.oracle_ax_classes.restype = None
+    L.oracle_cg_classes.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp, i32, i32, f64, i32, dp,
+                                    ctypes.POINTER(ctypes.c_int), lp, lp, i32]
+    L.oracle_set_threads.argtypes = [i32]
+    L.oracle_set_threads.restype = i32
+    return L
+
+
+def timing_lib(build: bool = True) -> ctypes.CDLL:
+    """The timing build (compiled here first unless build=False and it exists)."""
+    global _lib_omp
+    if _lib_omp is None:
+        if build or not os.path.exists(_LIB_OMP):
+            build_timing()
+        _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+    return _lib_omp
 
 
 def lib() -> ctypes.CDLL:
@@ -65,6 +105,7 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int)]
         L.oracle_cg.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp, i32, i32, f64, i32, dp, dp, dp, dp,
                                 ctypes.POINTER(ctypes.c_int)]
+        _declare(L)
         _lib = L
     return _lib
 
@@ -187,6 +228,42 @@ class Mesh:
         st = lib().oracle_pcg(self.E, self.N, _p(self.D), _p(self.geo), _p(self.map, ctypes.c_int64), self.NG, lam,
                               _p(inv), _p(b), _p(x), max_iter, fixed_iters, rtol, int(compensated), _p(res),
                               ctypes.byref(it))
+        j = it.value
+        return dict(x=x, iters=j, status=st, res=res[: j + 1])
+
+    def classes(self):
+        """The 8 element classes of the box, (ex mod 2, ey mod 2, ez mod 2): elements of
+        one class share no node.  Returns (order, offsets) as int64 arrays."""
+        e = np.arange(self.E, dtype=np.int64)
+        ex, ey, ez = e % self.nx, (e // self.nx) % self.ny, e // (self.nx * self.ny)
+        key = (ex % 2) + 2 * (ey % 2) + 4 * (ez % 2)
+        order = np.argsort(key, kind="stable").astype(np.int64)
+        offsets = np.searchsorted(key[order], np.arange(9)).astype(np.int64)
+        return order, offsets
+
+    def ax_classes(self, x: np.ndarray, lam: float, L: ctypes.CDLL | None = None) -> np.ndarray:
+        """y = A x with the elements swept class by class (on the timing build's
+        threads when L is the timing library)."""
+        L = L or lib()
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(self.NG)
+        order, offsets = self.classes()
+        L.oracle_ax_classes(self.E, self.N, _p(self.D), _p(self.geo), _p(self.map, ctypes.c_int64), self.NG, lam,
+                            _p(x), _p(y), _p(order, ctypes.c_int64), _p(offsets, ctypes.c_int64), 8)
+        return y
+
+    def cg_classes(self, b: np.ndarray, lam: float, *, fixed_iters: int = 0, max_iter: int = 1000,
+                   rtol: float = 1e-8, compensated: bool = True, L: ctypes.CDLL | None = None):
+        """Algorithm 1 from x0 = 0 with the class-by-class operator.  Returns dict(x, iters, status, res)."""
+        L = L or lib()
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros(self.NG)
+        res = np.zeros(max(fixed_iters, max_iter) + 1)
+        it = ctypes.c_int(0)
+        order, offsets = self.classes()
+        st = L.oracle_cg_classes(self.E, self.N, _p(self.D), _p(self.geo), _p(self.map, ctypes.c_int64), self.NG,
+                                 lam, _p(b), _p(x), max_iter, fixed_iters, rtol, int(compensated), _p(res),
+                                 ctypes.byref(it), _p(order, ctypes.c_int64), _p(offsets, ctypes.c_int64), 8)
         j = it.value
         return dict(x=x, iters=j, status=st, res=res[: j + 1])
 

@@ -13,6 +13,11 @@
  *     states (sum factorisation IS the paper's definition of the gradient:
  *     the Kronecker form of the 3D derivative in the NekBone section);
  *   - built with gcc -O2 -ffp-contract=off, so no FMA contraction happens.
+ * A second build of this file (-O3 -march=native -fopenmp, still without
+ * contraction) is the benchmark's CPU baseline: there the vector loops run on
+ * several threads and oracle_ax_classes / oracle_cg_classes sweep the elements
+ * class by class (elements of one class share no node); the parity tests use
+ * the single-threaded build.
  *
  * Notation (NekBone section): E elements, degree N, Np = (N+1)^3 local nodes per
  * element, N_L = E*Np, N_G assembled DOFs.  Local node (a,b,c) of an element has
@@ -30,6 +35,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Counter-based random numbers: splitmix64 (Steele, Lea & Flood, "Fast      */
@@ -338,63 +346,129 @@ int oracle_geometry(int nx, int ny, int nz, int N, const double *V, int mass_kin
 /* A map entry -1 (a Dirichlet boundary node) has no DOF: Z puts 0 there and  */
 /* Z^T drops its value.                                                       */
 /* ------------------------------------------------------------------------ */
-void oracle_ax(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
-               double lambda, const double *x, double *y)
+/* Work arrays of one element's operator application, (N+1)^3 doubles each. */
+typedef struct {
+    double *q, *qr, *qs, *qt, *fr, *fs, *ft, *ye;
+} ax_work;
+
+static void ax_work_alloc(ax_work *w, int64_t Np)
+{
+    w->q = malloc(sizeof(double) * Np);
+    w->qr = malloc(sizeof(double) * Np); w->qs = malloc(sizeof(double) * Np); w->qt = malloc(sizeof(double) * Np);
+    w->fr = malloc(sizeof(double) * Np); w->fs = malloc(sizeof(double) * Np); w->ft = malloc(sizeof(double) * Np);
+    w->ye = malloc(sizeof(double) * Np);
+}
+
+static void ax_work_free(ax_work *w)
+{
+    free(w->q); free(w->qr); free(w->qs); free(w->qt); free(w->fr); free(w->fs); free(w->ft); free(w->ye);
+}
+
+/* Element e's share of the operator: y += Z_e^T (D^T G^e D + lambda C^e) Z_e x. */
+static void ax_element(int64_t e, int N, const double *D, const double *geo, const int64_t *map, double lambda,
+                       const double *x, double *y, ax_work *w)
 {
     int n1 = N + 1;
     int64_t Np = (int64_t)n1 * n1 * n1;
-    double *q = malloc(sizeof(double) * Np);
-    double *qr = malloc(sizeof(double) * Np), *qs = malloc(sizeof(double) * Np), *qt = malloc(sizeof(double) * Np);
-    double *fr = malloc(sizeof(double) * Np), *fs = malloc(sizeof(double) * Np), *ft = malloc(sizeof(double) * Np);
-    double *ye = malloc(sizeof(double) * Np);
+    double *q = w->q, *qr = w->qr, *qs = w->qs, *qt = w->qt, *fr = w->fr, *fs = w->fs, *ft = w->ft, *ye = w->ye;
 #define IDX(a, b, c) ((a) + n1 * ((b) + n1 * (c)))
-    for (int64_t g = 0; g < NG; ++g) y[g] = 0.0;
-    for (int64_t e = 0; e < E; ++e) {
-        const int64_t *me = map + e * Np;
-        const double *ge = geo + e * 7 * Np;
-        /* Z: gather the element's nodal values from the assembled vector */
-        for (int64_t n = 0; n < Np; ++n) q[n] = me[n] >= 0 ? x[me[n]] : 0.0;
-        /* D: reference gradient */
-        for (int c = 0; c <= N; ++c)
-            for (int b = 0; b <= N; ++b)
-                for (int a = 0; a <= N; ++a) {
-                    double sr = 0.0, ss = 0.0, st = 0.0;
-                    for (int m = 0; m <= N; ++m) {
-                        sr += D[a * n1 + m] * q[IDX(m, b, c)];
-                        ss += D[b * n1 + m] * q[IDX(a, m, c)];
-                        st += D[c * n1 + m] * q[IDX(a, b, m)];
-                    }
-                    qr[IDX(a, b, c)] = sr;
-                    qs[IDX(a, b, c)] = ss;
-                    qt[IDX(a, b, c)] = st;
+    const int64_t *me = map + e * Np;
+    const double *ge = geo + e * 7 * Np;
+    /* Z: gather the element's nodal values from the assembled vector */
+    for (int64_t n = 0; n < Np; ++n) q[n] = me[n] >= 0 ? x[me[n]] : 0.0;
+    /* D: reference gradient */
+    for (int c = 0; c <= N; ++c)
+        for (int b = 0; b <= N; ++b)
+            for (int a = 0; a <= N; ++a) {
+                double sr = 0.0, ss = 0.0, st = 0.0;
+                for (int m = 0; m <= N; ++m) {
+                    sr += D[a * n1 + m] * q[IDX(m, b, c)];
+                    ss += D[b * n1 + m] * q[IDX(a, m, c)];
+                    st += D[c * n1 + m] * q[IDX(a, b, m)];
                 }
-        /* G^e: pointwise symmetric metric */
-        for (int64_t n = 0; n < Np; ++n) {
-            double Grr = ge[0 * Np + n], Grs = ge[1 * Np + n], Grt = ge[2 * Np + n];
-            double Gss = ge[3 * Np + n], Gst = ge[4 * Np + n], Gtt = ge[5 * Np + n];
-            fr[n] = Grr * qr[n] + Grs * qs[n] + Grt * qt[n];
-            fs[n] = Grs * qr[n] + Gss * qs[n] + Gst * qt[n];
-            ft[n] = Grt * qr[n] + Gst * qs[n] + Gtt * qt[n];
-        }
-        /* D^T: divergence, plus the lambda-weighted mass term */
-        for (int c = 0; c <= N; ++c)
-            for (int b = 0; b <= N; ++b)
-                for (int a = 0; a <= N; ++a) {
-                    double s = 0.0;
-                    for (int m = 0; m <= N; ++m) {
-                        s += D[m * n1 + a] * fr[IDX(m, b, c)];
-                        s += D[m * n1 + b] * fs[IDX(a, m, c)];
-                        s += D[m * n1 + c] * ft[IDX(a, b, m)];
-                    }
-                    int64_t n = IDX(a, b, c);
-                    ye[n] = s + lambda * ge[6 * Np + n] * q[n];
-                }
-        /* Z^T: assemble (gather-sum) into the global vector */
-        for (int64_t n = 0; n < Np; ++n)
-            if (me[n] >= 0) y[me[n]] += ye[n];
+                qr[IDX(a, b, c)] = sr;
+                qs[IDX(a, b, c)] = ss;
+                qt[IDX(a, b, c)] = st;
+            }
+    /* G^e: pointwise symmetric metric */
+    for (int64_t n = 0; n < Np; ++n) {
+        double Grr = ge[0 * Np + n], Grs = ge[1 * Np + n], Grt = ge[2 * Np + n];
+        double Gss = ge[3 * Np + n], Gst = ge[4 * Np + n], Gtt = ge[5 * Np + n];
+        fr[n] = Grr * qr[n] + Grs * qs[n] + Grt * qt[n];
+        fs[n] = Grs * qr[n] + Gss * qs[n] + Gst * qt[n];
+        ft[n] = Grt * qr[n] + Gst * qs[n] + Gtt * qt[n];
     }
+    /* D^T: divergence, plus the lambda-weighted mass term */
+    for (int c = 0; c <= N; ++c)
+        for (int b = 0; b <= N; ++b)
+            for (int a = 0; a <= N; ++a) {
+                double s = 0.0;
+                for (int m = 0; m <= N; ++m) {
+                    s += D[m * n1 + a] * fr[IDX(m, b, c)];
+                    s += D[m * n1 + b] * fs[IDX(a, m, c)];
+                    s += D[m * n1 + c] * ft[IDX(a, b, m)];
+                }
+                int64_t n = IDX(a, b, c);
+                ye[n] = s + lambda * ge[6 * Np + n] * q[n];
+            }
+    /* Z^T: assemble (gather-sum) into the global vector */
+    for (int64_t n = 0; n < Np; ++n)
+        if (me[n] >= 0) y[me[n]] += ye[n];
 #undef IDX
-    free(q); free(qr); free(qs); free(qt); free(fr); free(fs); free(ft); free(ye);
+}
+
+/* Element classes for a parallel sweep: the elements order[cls[k] .. cls[k+1])
+ * form class k, and no two elements of one class share a global node (on a box:
+ * the 8 classes of (ex mod 2, ey mod 2, ez mod 2)).  A NULL class list means
+ * every element in index order, one at a time. */
+typedef struct {
+    const int64_t *order;
+    const int64_t *cls;
+    int ncls;
+} elem_classes;
+
+static void ax_apply(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+                     double lambda, const double *x, double *y, const elem_classes *ec)
+{
+    int n1 = N + 1;
+    int64_t Np = (int64_t)n1 * n1 * n1;
+#pragma omp parallel for schedule(static) if (NG >= 65536)
+    for (int64_t g = 0; g < NG; ++g) y[g] = 0.0;
+    if (!ec) {
+        ax_work w;
+        ax_work_alloc(&w, Np);
+        for (int64_t e = 0; e < E; ++e) ax_element(e, N, D, geo, map, lambda, x, y, &w);
+        ax_work_free(&w);
+        return;
+    }
+    /* the timing build (OpenMP): threads share the elements of one class, which
+     * write disjoint entries of y; the classes follow each other */
+#pragma omp parallel
+    {
+        ax_work w;
+        ax_work_alloc(&w, Np);
+        for (int k = 0; k < ec->ncls; ++k) {
+#pragma omp for schedule(static)
+            for (int64_t i = ec->cls[k]; i < ec->cls[k + 1]; ++i)
+                ax_element(ec->order[i], N, D, geo, map, lambda, x, y, &w);
+        }
+        ax_work_free(&w);
+    }
+}
+
+void oracle_ax(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+               double lambda, const double *x, double *y)
+{
+    ax_apply(E, N, D, geo, map, NG, lambda, x, y, NULL);
+}
+
+/* The same operator with the elements swept class by class (see elem_classes):
+ * the CPU baseline's multi-threaded timing; the parity tests use oracle_ax. */
+void oracle_ax_classes(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+                       double lambda, const double *x, double *y, const int64_t *order, const int64_t *cls, int ncls)
+{
+    elem_classes ec = {order, cls, ncls};
+    ax_apply(E, N, D, geo, map, NG, lambda, x, y, &ec);
 }
 
 /* The diagonal of the assembled operator, for the Jacobi preconditioner (a
@@ -442,7 +516,7 @@ void oracle_diag(int64_t E, int N, const double *D, const double *geo, const int
 
 /* Dot product; compensated (Neumaier) when `compensated` is set, else plain
  * left-to-right.  The paper leaves the summation order open. */
-static double dot(int64_t n, const double *u, const double *v, int compensated)
+static double dot_serial(int64_t n, const double *u, const double *v, int compensated)
 {
     double s = 0.0, comp = 0.0;
     for (int64_t i = 0; i < n; ++i) {
@@ -454,6 +528,28 @@ static double dot(int64_t n, const double *u, const double *v, int compensated)
         s = sum;
     }
     return s + comp;
+}
+
+static double dot(int64_t n, const double *u, const double *v, int compensated)
+{
+#ifdef _OPENMP
+    /* the timing build with several threads: each thread sums one contiguous
+     * block as above, and the block sums are added in block order */
+    int nt = omp_get_max_threads();
+    if (nt > 1 && n >= 65536) {
+        double part[256];
+        if (nt > 256) nt = 256;
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+        for (int k = 0; k < nt; ++k) {
+            int64_t lo = n * k / nt, hi = n * (k + 1) / nt;
+            part[k] = dot_serial(hi - lo, u + lo, v + lo, compensated);
+        }
+        double s = 0.0;
+        for (int k = 0; k < nt; ++k) s += part[k];
+        return s;
+    }
+#endif
+    return dot_serial(n, u, v, compensated);
 }
 
 /*
@@ -471,12 +567,14 @@ static double dot(int64_t n, const double *u, const double *v, int compensated)
  * alpha/beta/pap) may be NULL: res[j] = sqrt(rho_j).
  * Returns 0 converged / fixed count done, 1 not converged, 2 breakdown.
  */
-int oracle_cg(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
-              double lambda, const double *b, double *x, int max_iter, int fixed_iters, double rtol,
-              int compensated, double *res, double *alpha_h, double *beta_h, double *pap_h, int *iters)
+static int cg_run(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+                  double lambda, const double *b, double *x, int max_iter, int fixed_iters, double rtol,
+                  int compensated, double *res, double *alpha_h, double *beta_h, double *pap_h, int *iters,
+                  const elem_classes *ec)
 {
     double *r = malloc(sizeof(double) * NG), *p = malloc(sizeof(double) * NG), *Ap = malloc(sizeof(double) * NG);
-    oracle_ax(E, N, D, geo, map, NG, lambda, x, Ap);
+    ax_apply(E, N, D, geo, map, NG, lambda, x, Ap, ec);
+#pragma omp parallel for schedule(static) if (NG >= 65536)
     for (int64_t g = 0; g < NG; ++g) {
         r[g] = b[g] - Ap[g];
         p[g] = r[g];
@@ -489,15 +587,18 @@ int oracle_cg(int64_t E, int N, const double *D, const double *geo, const int64_
     if (fixed_iters <= 0 && sqrt(rho) <= rtol * bnorm) status = 0;
     while (status == 1 && j < limit) {
         if (rho == 0.0) { status = 0; break; }
-        oracle_ax(E, N, D, geo, map, NG, lambda, p, Ap);
+        ax_apply(E, N, D, geo, map, NG, lambda, p, Ap, ec);
         double pAp = dot(NG, p, Ap, compensated);
         if (pap_h) pap_h[j] = pAp;
         if (!(pAp > 0.0)) { status = 2; break; }
         double alpha = rho / pAp;
+#pragma omp parallel for schedule(static) if (NG >= 65536)
         for (int64_t g = 0; g < NG; ++g) x[g] = x[g] + alpha * p[g];
+#pragma omp parallel for schedule(static) if (NG >= 65536)
         for (int64_t g = 0; g < NG; ++g) r[g] = r[g] - alpha * Ap[g];
         double rho_new = dot(NG, r, r, compensated);
         double beta = rho_new / rho;
+#pragma omp parallel for schedule(static) if (NG >= 65536)
         for (int64_t g = 0; g < NG; ++g) p[g] = r[g] + beta * p[g];
         if (alpha_h) alpha_h[j] = alpha;
         if (beta_h) beta_h[j] = beta;
@@ -510,6 +611,39 @@ int oracle_cg(int64_t E, int N, const double *D, const double *geo, const int64_
     if (iters) *iters = j;
     free(r); free(p); free(Ap);
     return status;
+}
+
+int oracle_cg(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+              double lambda, const double *b, double *x, int max_iter, int fixed_iters, double rtol,
+              int compensated, double *res, double *alpha_h, double *beta_h, double *pap_h, int *iters)
+{
+    return cg_run(E, N, D, geo, map, NG, lambda, b, x, max_iter, fixed_iters, rtol, compensated, res, alpha_h,
+                  beta_h, pap_h, iters, NULL);
+}
+
+/* Algorithm 1 as oracle_cg, with the operator swept class by class
+ * (oracle_ax_classes): the CPU baseline's multi-threaded timing. */
+int oracle_cg_classes(int64_t E, int N, const double *D, const double *geo, const int64_t *map, int64_t NG,
+                      double lambda, const double *b, double *x, int max_iter, int fixed_iters, double rtol,
+                      int compensated, double *res, int *iters, const int64_t *order, const int64_t *cls,
+                      int ncls)
+{
+    elem_classes ec = {order, cls, ncls};
+    return cg_run(E, N, D, geo, map, NG, lambda, b, x, max_iter, fixed_iters, rtol, compensated, res, NULL, NULL,
+                  NULL, iters, &ec);
+}
+
+/* Threads of the timing build (OpenMP); the parity build is single-threaded
+ * and reports 1. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /*

@@ -11,6 +11,11 @@ the operator's launches.
 
   python -m paper_2202_12477_amd.profile_ax [--case box32_N7_affine | sweepN] [--launches K] [--fp32 | --gather]
       [--pcg K]
+  python -m paper_2202_12477_amd.profile_ax --cases sweep9 sweep12 sweep2:fp32 ... [--launches K]
+
+--cases runs several operators one after the other in one process (a case with
+the suffix ":fp32" is the FP32 operator on that mesh), so that one profiler
+pass covers them all; each case's launches are announced on stdout first.
 
 --pcg K then also runs K fixed iterations of Jacobi-preconditioned FP64 CG on
 the same mesh (its vector kernels: residual_kernel<double, true>,
@@ -34,7 +39,10 @@ def main():
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--gather", action="store_true")
     ap.add_argument("--pcg", type=int, default=0)
+    ap.add_argument("--cases", nargs="*", default=None, help="several cases (suffix :fp32 for the FP32 operator)")
     args = ap.parse_args()
+    if args.cases:
+        return run_cases(args.cases, args.launches)
     if args.fp32 and args.gather:
         ap.error("the two-phase operator is FP64 only")
 
@@ -82,6 +90,45 @@ def main():
     torch.cuda.synchronize()
     print(f"stream probe n={STREAM_N} read_bytes={8 * 8 * STREAM_N} write_bytes={8 * STREAM_N} "
           f"launches={args.launches}", flush=True)
+
+
+def run_cases(cases, launches):
+    """Operator launches on several order-sweep meshes (or the named boxes), then the probe."""
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import torch
+
+    import inputs
+    import paper_2202_12477_amd as hb
+
+    named = {k.name: k for k in (inputs.PLAIN_SMALL, inputs.PLAIN_LARGE)}
+    for spec in cases:
+        name, _, kind = spec.partition(":")
+        fp32 = kind == "fp32"
+        c = inputs.order_sweep_case(int(name[5:])) if name.startswith("sweep") else named[name]
+        m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=fp32)
+        b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+        hb.rhs_uniform(b, c.rhs_seed)
+        print(f"operator {c.name} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={launches} "
+              f"{'fp32' if fp32 else 'fp64'} schedule={hb.get_schedule(c.N, hb.PREC_FP32_RR if fp32 else hb.PREC_FP64)}",
+              flush=True)
+        if fp32:
+            y = torch.zeros(m.NG, dtype=torch.float32, device="cuda")
+            for _ in range(launches):
+                m.ax_f32(c.lam, b, y)
+        else:
+            y = torch.zeros_like(b)
+            for _ in range(launches):
+                m.ax_add(c.lam, b, y)
+        torch.cuda.synchronize()
+        m.close()
+        del b, y
+    inp = torch.ones(8 * STREAM_N, dtype=torch.float64, device="cuda")
+    out = torch.empty(STREAM_N, dtype=torch.float64, device="cuda")
+    for _ in range(launches):
+        hb.stream_probe(inp, out)
+    torch.cuda.synchronize()
+    print(f"stream probe n={STREAM_N} read_bytes={8 * 8 * STREAM_N} write_bytes={8 * STREAM_N} "
+          f"launches={launches}", flush=True)
 
 
 if __name__ == "__main__":

@@ -131,14 +131,31 @@ def test_refinement_argument_errors():
     assert e.value.status == hb.HB_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("prec", MIXED)
-@pytest.mark.parametrize("N", [3, 7])
-def test_refinement_order_sweep_size(N, prec):
-    """Order-sweep mesh (about 2^24 local nodes, jittered) solved to 1e-10 by refinement;
-    the FP64 oracle confirms the true residual."""
+@pytest.mark.parametrize("N", list(range(1, 16)))
+def test_refinement_order_sweep(N):
+    """The order sweep at every degree: the sweep mesh (about 2^24 local nodes,
+    jittered) solved to 1e-10 by restarted refinement and by residual replacement,
+    both with the FP32 operator; the oracle's FP64 operator confirms each true
+    residual (one oracle mesh per degree serves both solves)."""
     c = inputs.order_sweep_case(N)
-    say(f"[case] mixed prec={prec} order sweep N={N} n={c.nx}")
-    m, b, x, res = solve_mixed(c, 1e-10, prec)
-    say(f"outer {res.outer_iters} inner {res.iters} fp64 {res.fp64_iters} res/b {res.res / res.bnorm:.2e}")
-    assert res.status == hb.HB_OK
-    assert oracle_true_residual(c, host(x)) <= 1.2e-10
+    m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=True)
+    b = torch.empty(m.NG, dtype=torch.float64, device=DEV)
+    hb.rhs_uniform(b, c.rhs_seed)
+    xs = {}
+    for prec in MIXED:
+        say(f"[case] mixed prec={prec} order sweep N={N} n={c.nx}")
+        x = torch.empty_like(b)
+        res = m.cg(c.lam, b, x, max_iter=40000, fixed_iters=False, rtol=1e-10, prec=prec)
+        say(f"N={N} prec={prec}: outer {res.outer_iters} inner {res.iters} fp64 {res.fp64_iters} "
+            f"res/b {res.res / res.bnorm:.2e}")
+        assert res.status == hb.HB_OK
+        assert res.res <= 1e-10 * res.bnorm
+        xs[prec] = host(x)
+    m.close()
+    ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+    bh = oracle.rhs(ref.NG, c.rhs_seed)
+    assert np.array_equal(host(b), bh)
+    for prec, x in xs.items():
+        tr = np.linalg.norm(bh - ref.ax(x, c.lam)) / np.linalg.norm(bh)
+        say(f"N={N} prec={prec}: oracle FP64 true residual {tr:.3e}")
+        assert tr <= 1.2e-10

@@ -14,6 +14,7 @@ import pytest
 import inputs
 import oracle
 from cg_envelope import compare_history, history_bar
+from conftest import golden_path
 from oracle import brute
 
 torch = pytest.importorskip("torch")
@@ -211,9 +212,18 @@ def test_cg_edge_cases():
     assert relerr(host(x), xs) <= 1e-12
 
 
+def load_history(name):
+    """Stored oracle history: (||r_j|| compensated, bar_j), written by tests/golden/make_cg_history.py."""
+    rows = np.array([[float(v) for v in l.split()] for l in open(golden_path(name))
+                     if l.strip() and not l.startswith("#")])
+    return rows[:, 1], rows[:, 3]
+
+
 def test_cg_large_config():
-    """32^3 affine, N=7: the first 30 residuals against the oracle; then the full
-    100-iteration solve checked by properties at full size."""
+    """32^3 affine, N=7, 100 fixed iterations: every residual against the oracle's
+    history (stored by a script that calls only the oracle) within the envelope of
+    tests/cg_envelope.py; the recursive residual at the end against the oracle's
+    true residual of the GPU iterate."""
     c = inputs.PLAIN_LARGE
     m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
     say("[case] large config CG")
@@ -223,13 +233,15 @@ def test_cg_large_config():
     res = m.cg(c.lam, b, x, max_iter=c.iters, fixed_iters=True)
     assert res.status == hb.HB_OK and res.iters == c.iters
     h = np.array(res.history)
-    assert np.all(np.isfinite(h)) and h[-1] < h[0]
+    href, bar = load_history("cg_history_box32_N7.txt")
+    assert len(href) == c.iters + 1
+    ratio = compare_history(h, href, bar)
+    say(f"history ratio to bar (100 iterations): {ratio:.3f}")
+    assert ratio <= 1.0
+    # recursive residual after 100 iterations agrees with the true one
     ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
     bh = oracle.rhs(m.NG, c.rhs_seed)
-    k = 30
-    out = ref.cg(bh, c.lam, fixed_iters=k)
-    assert np.max(np.abs(h[: k + 1] - out["res"]) / out["res"]) <= 1e-10
-    # recursive residual after 100 iterations agrees with the true one
+    assert np.array_equal(host(b), bh)
     rtrue = np.linalg.norm(bh - ref.ax(host(x), c.lam))
     assert abs(rtrue - h[-1]) <= 1e-9 * h[0]
     m.close()

@@ -114,3 +114,31 @@ def test_manufactured_solution_converges_spectrally():
     for a, b in zip(errs, errs[1:]):
         assert b < a / 10, errs
     assert errs[-1] < 1e-6, errs
+
+
+def test_stored_large_history_pinned():
+    """The stored oracle history of the 32^3 N=7 benchmark (tests/golden/cg_history_box32_N7.txt,
+    written by make_cg_history.py from the oracle) against an independent route: r_0 = b
+    (x0 = 0), and the first iterations of textbook CG with the affine box's Kronecker
+    closed form of A (brute.affine_box_ax), which shares no code with oracle.c."""
+    from conftest import golden_path
+
+    rows = np.array([[float(v) for v in l.split()] for l in open(golden_path("cg_history_box32_N7.txt"))
+                     if l.strip() and not l.startswith("#")])
+    c = inputs.PLAIN_LARGE
+    assert rows.shape == (c.iters + 1, 4) and np.array_equal(rows[:, 0], np.arange(c.iters + 1))
+    href, alt, bar = rows[:, 1], rows[:, 2], rows[:, 3]
+    assert np.all(bar >= 1e-10) and np.all(np.abs(href - alt) <= bar * np.abs(href) / 10 + 1e-300)
+    b = rhs((c.nx * c.N + 1) ** 3, c.rhs_seed)
+    assert href[0] == pytest.approx(np.linalg.norm(b), rel=1e-14)
+    k = 3
+    x, r = np.zeros_like(b), b.copy()
+    p, rho = r.copy(), r @ r
+    for j in range(1, k + 1):
+        Ap = brute.affine_box_ax(c.nx, c.ny, c.nz, c.N, c.lam, p)
+        alpha = rho / (p @ Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        rho, rho_old = r @ r, rho
+        p = r + (rho / rho_old) * p
+        assert math.sqrt(rho) == pytest.approx(href[j], rel=1e-11), j
