@@ -237,6 +237,26 @@ typedef struct {
 hb_status hb_cg_solve(hb_mesh mesh, double lambda, const double *dev_b, double *dev_x, const hb_cg_opts *opts,
                       hb_cg_result *result, double *host_res_hist, void *stream);
 
+/* hb_cg_solve without any allocation, for callers that cannot allocate device
+ * memory (code under HIP stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, algorithm, kernels and results as
+ * hb_cg_solve in HB_PREC_FP64 (plain or HB_PRECOND_JACOBI, fixed count or
+ * tolerance), but the workspace (r, p, Ap, block partials, device state, the
+ * rho and ||r|| histories, 1/diag(A)) lives in one static device buffer of
+ * 64 MiB per GPU that the library holds until the process ends; no hipMalloc,
+ * hipFree, pinned host allocation or graph is made.  The workspace needs
+ * 24 N_G (32 N_G with Jacobi) + 16 (max_iter + 1) bytes plus the block
+ * partials: N_G up to about 2.7M DOFs at 100 iterations.  Larger solves,
+ * opts->prec other than HB_PREC_FP64 and opts->graph_k != 0 are rejected with
+ * HB_ERR_INVALID_ARG before any device work.  Every call on one GPU shares
+ * that GPU's buffer: calls that overlap in time on the same GPU (other host
+ * threads, or other streams with work still in flight) race and give wrong
+ * results; calls serialised on one stream are safe.  The Jacobi diagonal is
+ * recomputed on every call (the buffer keeps no state between calls).
+ * Synchronises `stream` before returning; returns what hb_cg_solve returns. */
+hb_status hb_cg_solve_noalloc(hb_mesh mesh, double lambda, const double *dev_b, double *dev_x,
+                              const hb_cg_opts *opts, hb_cg_result *result, double *host_res_hist, void *stream);
+
 /* Batched solve of independent problems (each its own mesh, lambda, b, x):
  * every problem runs the same algorithm as hb_cg_solve (HB_PREC_FP64, fixed
  * count or tolerance; or HB_PREC_FP32_RR), but all problems advance together:

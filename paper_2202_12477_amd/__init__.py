@@ -39,7 +39,7 @@ PRECOND_JACOBI = 1
 # Every entry point of include/hbmi.h, in declaration order.
 EXPORTS = (
     "hb_mesh_create", "hb_mesh_destroy", "hb_mesh_query", "hb_mesh_export", "hb_rhs_uniform", "hb_ax", "hb_ax_add",
-    "hb_ax_f32", "hb_cg_solve", "hb_batch_solve", "hb_engine_footprint", "hb_engine_create", "hb_engine_destroy",
+    "hb_ax_f32", "hb_cg_solve", "hb_cg_solve_noalloc", "hb_batch_solve", "hb_engine_footprint", "hb_engine_create", "hb_engine_destroy",
     "hb_engine_submit", "hb_engine_step", "hb_engine_poll", "hb_get_schedule", "hb_set_schedule", "hb_autotune",
     "hb_stream_probe", "hb_status_string", "hb_last_error",
 )
@@ -117,6 +117,7 @@ def lib() -> ctypes.CDLL:
         "hb_ax_add": [vp, f64, vp, vp, vp],
         "hb_ax_f32": [vp, f64, vp, vp, vp],
         "hb_cg_solve": [vp, f64, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp, vp],
+        "hb_cg_solve_noalloc": [vp, f64, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp, vp],
         "hb_batch_solve": [i32, vp, vp, vp, vp, ctypes.POINTER(_CgOpts), ctypes.POINTER(_CgResult), vp],
         "hb_stream_probe": [vp, vp, i64, vp],
         "hb_engine_footprint": [ctypes.POINTER(_MeshDesc), i32, i32, ctypes.POINTER(ctypes.c_size_t)],
@@ -289,6 +290,27 @@ class Mesh:
         if history:
             k = res.outer_iters if prec != PREC_FP64 else res.iters
             out.history = list(hist[: min(k, max_iter) + 1])
+        return out
+
+    def cg_noalloc(self, lam: float, b, x, *, max_iter: int = 100, fixed_iters: bool = True, rtol: float = 0.0,
+                   x0_zero: bool = True, check_every: int = 0, history: bool = True, precond: int = PRECOND_NONE,
+                   stream=None, raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)) -> CgResult:
+        """FP64 CG as cg(), with the workspace in the library's static device buffer
+        (hb_cg_solve_noalloc: no device allocation; calls overlapping on one GPU race)."""
+        import torch
+
+        if b.numel() != self.NG or x.numel() != self.NG:
+            raise ValueError("vectors must have N_G entries")
+        opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, PREC_FP64, 0, 0.0, 0, precond)
+        res = _CgResult()
+        hist = (ctypes.c_double * (max_iter + 1))() if history else None
+        st = lib().hb_cg_solve_noalloc(self.handle, lam, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                                       ctypes.byref(opts), ctypes.byref(res), hist, _stream(stream))
+        if st in raise_on:
+            _check(st, "hb_cg_solve_noalloc")
+        out = CgResult(res.iters, res.status, res.res0, res.res, res.bnorm)
+        if history:
+            out.history = list(hist[: min(res.iters, max_iter) + 1])
         return out
 
 

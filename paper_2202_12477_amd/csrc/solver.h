@@ -19,6 +19,10 @@ hb_status read_state(CgWork &w, hipStream_t s);
 hb_status read_norm(CgWork &w, hipStream_t s, double *out);
 hb_status apply_op(const hb_mesh_s *m, double l, const double *x, double *y, double *part, CgState *st, hipStream_t s);
 hb_status apply_op(const hb_mesh_s *m, double l, const double *x, float *y, double *part, CgState *st, hipStream_t s);
+// One CG iteration (Algorithm 1, loop body) on the workspace w: the operator
+// step with p.Ap, alpha, the residual step with r.r, beta, the update.
+template <typename TAp>
+hb_status enqueue_iteration(hb_mesh_s *m, CgWork &w, double lambda, double *x, TAp *Ap, hipStream_t s);
 template <typename TAp>
 hb_status cg_iterate(hb_mesh_s *m, double lambda, double *x, TAp *Ap, int max_iter, bool fixed, int check_every,
                      hipStream_t s);

@@ -102,9 +102,8 @@ hb_status read_state(CgWork &w, hipStream_t s)
 // type is TAp: Ap = A p with p.Ap fused, alpha, r -= alpha Ap with r.r, beta,
 // x += alpha p and p = r + beta p (which also clears Ap for the next operator).
 template <typename TAp>
-static hb_status enqueue_iteration(hb_mesh_s *m, double lambda, double *x, TAp *Ap, hipStream_t s)
+hb_status enqueue_iteration(hb_mesh_s *m, CgWork &w, double lambda, double *x, TAp *Ap, hipStream_t s)
 {
-    CgWork &w = m->cg;
     const int64_t n = m->NG;
     hb_status e;
     if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, s))) return e;
@@ -136,7 +135,7 @@ static hb_status iteration_graph(hb_mesh_s *m, double lambda, double *x, TAp *Ap
     const int epoch = ax_schedule_epoch();
     HB_HIP(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
     hb_status st = HB_OK;
-    for (int i = 0; i < k && st == HB_OK; ++i) st = enqueue_iteration<TAp>(m, lambda, x, Ap, w.cap);
+    for (int i = 0; i < k && st == HB_OK; ++i) st = enqueue_iteration<TAp>(m, w, lambda, x, Ap, w.cap);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(w.cap, &graph);
     if (st != HB_OK || e != hipSuccess) {
@@ -186,7 +185,7 @@ hb_status cg_iterate(hb_mesh_s *m, double lambda, double *x, TAp *Ap, int max_it
             for (int i = 0; i < (k + w.graph_k - 1) / w.graph_k; ++i) HB_HIP(hipGraphLaunch(graph, s));
         } else {
             for (int i = 0; i < k; ++i)
-                if ((st = enqueue_iteration<TAp>(m, lambda, x, Ap, s))) return st;
+                if ((st = enqueue_iteration<TAp>(m, w, lambda, x, Ap, s))) return st;
         }
         if ((st = read_state(w, s))) return st;
         done_iters = w.host_state->iters;
@@ -305,6 +304,7 @@ hb_status solve_replace(hb_mesh_s *m, double lambda, const double *b, double *x,
 }
 
 
+template hb_status enqueue_iteration<double>(hb_mesh_s *, CgWork &, double, double *, double *, hipStream_t);
 template hb_status cg_iterate<double>(hb_mesh_s *, double, double *, double *, int, bool, int, hipStream_t);
 template hb_status cg_iterate<float>(hb_mesh_s *, double, double *, float *, int, bool, int, hipStream_t);
 template hb_status run_cg<double>(hb_mesh_s *, double, const double *, double *, double *, int, int, double, int,
