@@ -96,8 +96,6 @@ def lib() -> ctypes.CDLL:
         L.oracle_vertices.argtypes = [i32, i32, i32, f64, u64, dp]
         L.oracle_map.argtypes = [i32, i32, i32, i32, lp]
         L.oracle_map_dirichlet.argtypes = [i32, i32, i32, i32, lp]
-        L.oracle_map_blocked.argtypes = [i32, i32, i32, i32, i32, lp]
-        L.oracle_map_blocked.restype = i64
         L.oracle_geometry.argtypes = [i32, i32, i32, i32, dp, i32, dp]
         L.oracle_ax.argtypes = [i64, i32, dp, dp, lp, i64, f64, dp, dp]
         L.oracle_ax.restype = None
@@ -159,9 +157,7 @@ MASS_INVDEG = 1  # A = S + lambda I   (c = inverse multiplicity W)
 class Mesh:
     """Box mesh of nx*ny*nz hexahedra of degree N on [0,1]^3: no masking, or with
     dirichlet=True homogeneous Dirichlet conditions on the boundary of the box (the
-    boundary nodes carry no DOF; N_G = (nx N - 1)(ny N - 1)(nz N - 1)).  DOFs are
-    numbered lexicographically, or with blocked=True skeleton DOFs first and each
-    element's interior DOFs after them (oracle_map_blocked; S = self.NS of them)."""
+    boundary nodes carry no DOF; N_G = (nx N - 1)(ny N - 1)(nz N - 1))."""
 
     nx: int
     ny: int
@@ -171,7 +167,6 @@ class Mesh:
     seed: int = 0
     mass: int = MASS_GWJ
     dirichlet: bool = False
-    blocked: bool = False
 
     def __post_init__(self):
         L = lib()
@@ -185,15 +180,8 @@ class Mesh:
         self.D = deriv(self.N)
         self.V = vertices(self.nx, self.ny, self.nz, self.jitter, self.seed)
         self.map = np.empty(self.NL, dtype=np.int64)
-        if self.blocked:
-            self.NS = int(L.oracle_map_blocked(self.nx, self.ny, self.nz, self.N, int(self.dirichlet),
-                                               _p(self.map, ctypes.c_int64)))
-            if self.NS < 0:
-                raise MemoryError("oracle_map_blocked: out of memory")
-        else:
-            (L.oracle_map_dirichlet if self.dirichlet else L.oracle_map)(self.nx, self.ny, self.nz, self.N,
-                                                                          _p(self.map, ctypes.c_int64))
-            self.NS = self.NG
+        (L.oracle_map_dirichlet if self.dirichlet else L.oracle_map)(self.nx, self.ny, self.nz, self.N,
+                                                                      _p(self.map, ctypes.c_int64))
         self.geo = np.empty(self.E * 7 * self.Np)
         st = L.oracle_geometry(self.nx, self.ny, self.nz, self.N, _p(self.V), self.mass, _p(self.geo))
         if st != 0:

@@ -239,62 +239,6 @@ void oracle_map_dirichlet(int nx, int ny, int nz, int N, int64_t *map)
             }
 }
 
-/* The same rows of Z under a second numbering of the global DOFs.  The
- * method leaves the numbering free (Z only has to send every local copy of a
- * node to the same DOF); this one splits the assembled vector in two blocks:
- *   1. the DOFs on the element skeleton (global node (I,J,K) with I, J or K a
- *      multiple of N: on a face, edge or vertex of an element, so possibly
- *      shared), in the lexicographic order of the global nodes;
- *   2. the DOFs strictly inside an element ((N-1)^3 per element, never
- *      shared), element after element in element order, each element's in its
- *      local order: S + e (N-1)^3 + (a-1) + (N-1)((b-1) + (N-1)(c-1)), where S
- *      is the size of block 1.
- * Built by counting: block 1 walks the global nodes of the first map's
- * numbering in ascending order and hands out labels to the skeleton ones.
- * dirichlet: the DOFs are those of oracle_map_dirichlet (a boundary node of the
- * box stays -1).  Returns S, or -1 if out of memory. */
-int64_t oracle_map_blocked(int nx, int ny, int nz, int N, int dirichlet, int64_t *map)
-{
-    int n1 = N + 1;
-    int64_t Np = (int64_t)n1 * n1 * n1;
-    int64_t E = (int64_t)nx * ny * nz;
-    int64_t gx = (int64_t)nx * N + 1, gy = (int64_t)ny * N + 1, gz = (int64_t)nz * N + 1;
-    int k = dirichlet ? 1 : 0; /* first DOF coordinate along each axis */
-    int64_t lx = gx - 2 * k, ly = gy - 2 * k, lz = gz - 2 * k;
-    int64_t NG = lx * ly * lz;
-    int64_t *lex = malloc(sizeof(int64_t) * (size_t)(E * Np));
-    int64_t *label = malloc(sizeof(int64_t) * (size_t)(NG > 0 ? NG : 1));
-    if (!lex || !label) {
-        free(lex);
-        free(label);
-        return -1;
-    }
-    if (dirichlet)
-        oracle_map_dirichlet(nx, ny, nz, N, lex);
-    else
-        oracle_map(nx, ny, nz, N, lex);
-    /* block 1: global node (I,J,K) has first-map index (I-k) + lx((J-k) + ly(K-k)) */
-    int64_t S = 0;
-    for (int64_t g = 0; g < NG; ++g) {
-        int64_t I = g % lx + k, J = (g / lx) % ly + k, K = g / (lx * ly) + k;
-        label[g] = -1;
-        if (I % N == 0 || J % N == 0 || K % N == 0) label[g] = S++;
-    }
-    /* block 2 */
-    int64_t ni = (int64_t)(N - 1) * (N - 1) * (N - 1);
-    for (int64_t e = 0; e < E; ++e)
-        for (int c = 1; c < N; ++c)
-            for (int b = 1; b < N; ++b)
-                for (int a = 1; a < N; ++a) {
-                    int64_t g = lex[e * Np + a + n1 * (b + n1 * c)];
-                    label[g] = S + e * ni + (a - 1) + (int64_t)(N - 1) * ((b - 1) + (int64_t)(N - 1) * (c - 1));
-                }
-    for (int64_t l = 0; l < E * Np; ++l) map[l] = lex[l] < 0 ? -1 : label[lex[l]];
-    free(lex);
-    free(label);
-    return S;
-}
-
 /* ------------------------------------------------------------------------ */
 /* Geometric factors (NekBone section: G^e is the symmetric 3x3 block of     */
 /* diagonal matrices holding the metric tensor combined with GLL weights).   */
