@@ -191,6 +191,15 @@ typedef struct {
     int32_t precond;     /* hb_precond: HB_PRECOND_JACOBI in every precision (HB_PREC_FP32_RR: each residual
                             replacement also recomputes r.z; HB_PREC_FP32_IR: the inner FP32 solves and the
                             FP64 fallback are preconditioned); hb_batch_solve: not with HB_PREC_FP32_IR */
+    int32_t persistent;  /* hb_batch_solve: 1 runs each segment of iterations as ONE persistent cooperative launch
+                            holding every running problem (each on its own workgroups, synchronised by barriers
+                            among those workgroups only; the whole iteration -- operator with p.Ap, alpha,
+                            residual with r.r, beta, update -- inside the launch), instead of one launch per
+                            (degree, precision) class and four per step and iteration.  Used for the segments
+                            whose running problems all have N in {3, 5, 7, 9} and are all plain or all Dirichlet
+                            boxes (others use the per-step launches); same results up to the order of the
+                            floating-point sums.  A barrier wait that times out ends the launch and the solve
+                            with HB_ERR_DEVICE.  Ignored by hb_cg_solve.  0: per-step launches */
 } hb_cg_opts;
 
 typedef struct {
@@ -201,6 +210,8 @@ typedef struct {
     double bnorm;        /* ||b|| */
     int32_t outer_iters; /* FP32_IR: refinement steps; FP32_RR: replacements (0 in FP64 mode) */
     int32_t fp64_iters;  /* mixed: FP64 CG iterations run after the FP32 operator stalled (0 if it did not) */
+    int32_t persistent_segments; /* hb_batch_solve with opts->persistent: segments of this problem's iterations
+                                    run inside persistent launches (0 elsewhere) */
 } hb_cg_result;
 
 /* Algorithm 1 on the assembled system A x = b: r0 = b - A x0, p = r0; per

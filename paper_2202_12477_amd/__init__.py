@@ -77,13 +77,13 @@ class _CgOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("graph_k", ctypes.c_int32),
-                ("precond", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class _CgResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("res0", ctypes.c_double),
                 ("res", ctypes.c_double), ("bnorm", ctypes.c_double), ("outer_iters", ctypes.c_int32),
-                ("fp64_iters", ctypes.c_int32)]
+                ("fp64_iters", ctypes.c_int32), ("persistent_segments", ctypes.c_int32)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -183,6 +183,7 @@ class CgResult:
     outer_iters: int = 0
     fp64_iters: int = 0
     history: "list[float] | None" = None
+    persistent_segments: int = 0
 
 
 class Mesh:
@@ -316,10 +317,11 @@ class Mesh:
 
 def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool = False, rtol: float = 1e-8,
                 x0_zero: bool = True, check_every: int = 0, prec: int = PREC_FP64, inner_rtol: float = 0.0,
-                graph_k: int = 0, precond: int = PRECOND_NONE, stream=None,
+                graph_k: int = 0, precond: int = PRECOND_NONE, persistent: bool = False, stream=None,
                 raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
     """Solve independent problems together (hb_batch_solve); returns (status, [CgResult]).
-    graph_k > 0: segments of graph_k iterations replayed from captured graphs."""
+    graph_k > 0: segments of graph_k iterations replayed from captured graphs; persistent: each segment
+    as one persistent launch holding every running problem (where their degrees and boxes allow)."""
     import torch
 
     n = len(meshes)
@@ -334,11 +336,12 @@ def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool 
     X = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64) for x in xs])
     R = (_CgResult * n)()
     opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, 0, inner_rtol, graph_k,
-                   precond)
+                   precond, int(persistent))
     st = lib().hb_batch_solve(n, H, L, B, X, ctypes.byref(opts), R, _stream(stream))
     if st in raise_on:
         _check(st, "hb_batch_solve")
-    return st, [CgResult(r.iters, r.status, r.res0, r.res, r.bnorm, r.outer_iters, r.fp64_iters) for r in R]
+    return st, [CgResult(r.iters, r.status, r.res0, r.res, r.bnorm, r.outer_iters, r.fp64_iters,
+                         persistent_segments=r.persistent_segments) for r in R]
 
 
 def request_footprint(nx: int, ny: int, nz: int, N: int, prec: int = PREC_FP64, max_iter: int = 100000,

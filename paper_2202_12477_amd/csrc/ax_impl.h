@@ -112,12 +112,13 @@ __device__ inline void atomic_add(gptr<T> p, T v)
 }
 
 // One tile of EPB elements starting at element tile*EPB: y += A x on them and,
-// with DOT, this block's sum of x_e . y_e written to *dot_out (thread 0).
+// with DOT, this block's sum of x_e . y_e, returned in every thread and written
+// to *dot_out (thread 0) unless dot_out is null.
 // Every thread of the block must call it (it synchronises the block).
 // (Always inlined: the single-problem and the batched kernel both call it, and
 // an out-of-line call would spill the whole register set.)
 template <int N, bool DOT, typename T, int V, bool MASK, bool LOCAL = false>
-__device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
+__device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
                                gptr<const T> __restrict__ geo, gptr<const T> __restrict__ Dm, T lambda,
                                gptr<const double> __restrict__ x, gptr<T> __restrict__ y,
                                gptr<double> __restrict__ dot_out)
@@ -345,8 +346,10 @@ __device__ __attribute__((always_inline)) inline void ax_tile(int64_t E, int64_t
             for (int c = 0; c < n1; ++c) v += static_cast<double>(q[c]) * static_cast<double>(yv[c]);
         }
         v = block_sum(v, red);
-        if (t == 0) *dot_out = v;
+        if (t == 0 && dot_out) *dot_out = v;
+        return v;
     }
+    return 0.0;
 }
 
 template <int N, bool DOT, typename T, int V, bool MASK>

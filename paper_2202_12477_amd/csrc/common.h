@@ -93,6 +93,17 @@ struct WorkItem {
     int32_t prob, idx;
 };
 
+// The persistent batched launch (persist.hip): workgroup -> (problem, rank
+// among the problem's workgroups), and per problem its workgroup count, its
+// iteration budget for the launch, its operator tiles and their order.
+struct PersistWg {
+    int32_t prob, rank;
+};
+struct PersistSlot {
+    TileWalk walk;
+    int32_t tiles, nwg, iters, pad;
+};
+
 // Per-mesh CG workspace (device), allocated on first use.
 struct CgWork {
     int64_t n = 0;         // N_G it was sized for
@@ -243,6 +254,22 @@ hb_status launch_batch_alpha(const int32_t *plist, int np, const BatchProb *prob
 hb_status launch_batch_residual(const WorkItem *items, int nitems, const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_beta(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_update(const WorkItem *items, int nitems, const BatchProb *probs, hipStream_t s);
+
+// The persistent batched launch (persist.hip): every running problem advances
+// up to slots[p].iters iterations inside one cooperative launch of `nwg`
+// workgroups, each problem on its own workgroups (wgs), synchronised by
+// per-problem barriers over the counters bar[p] (zero before the launch).  A
+// barrier wait that exceeds its spin limit sets *err and ends the launch.
+// Degrees the kernel is compiled for, its workgroup size, and how many of its
+// workgroups the device holds at once (0 if it cannot be launched).
+bool persist_degree(int N);
+constexpr int kPersistThreads = 256;
+int persist_capacity();
+// Operator tiles of an N-degree box of E elements in the persistent kernel, and their walk.
+int persist_tiles(int N, int64_t E);
+TileWalk persist_walk(int N, int64_t nx, int64_t ny, int64_t nz);
+hb_status launch_batch_persistent(bool dirichlet, const PersistWg *wgs, int nwg, const PersistSlot *slots,
+                                  const BatchProb *probs, uint32_t *bar, int32_t *err, hipStream_t s);
 
 // 8:1 streaming probe (stream.hip).
 hb_status launch_stream_probe(const double *in, double *out, int64_t n, hipStream_t s);

@@ -38,10 +38,11 @@ class BatchRunner {
     {
         if (gexec_) (void)hipGraphExecDestroy(gexec_);
         if (cap_s_) (void)hipStreamDestroy(cap_s_);
-        for (void *p : {(void *)probs_, (void *)states_, (void *)items_, (void *)plist_, (void *)norms_})
+        for (void *p : {(void *)probs_, (void *)states_, (void *)items_, (void *)plist_, (void *)norms_,
+                        (void *)pwgs_, (void *)pslots_, (void *)pbar_})
             if (p) (void)hipFree(p);
         for (void *p : {(void *)h_probs_, (void *)h_states_, (void *)h_items_, (void *)h_plist_, (void *)h_norms_,
-                        (void *)h_rho_})
+                        (void *)h_rho_, (void *)h_pwgs_, (void *)h_pslots_, (void *)h_perr_})
             if (p) (void)hipHostFree(p);
     }
 
@@ -63,6 +64,12 @@ class BatchRunner {
         return HB_OK;
     }
 
+    // Run each step as one persistent launch when the running problems allow it
+    // (persist.hip); otherwise, and for the steps where they do not, per-step launches.
+    void use_persistent(bool on) { persistent_ = on; }
+    // Steps run as one persistent launch so far.
+    int persistent_steps() const { return persist_steps_; }
+
     int free_slot() const
     {
         for (int i = 0; i < cap_; ++i)
@@ -76,11 +83,16 @@ class BatchRunner {
         return n;
     }
     bool finished(int i) const { return slots_[i].used && slots_[i].finished; }
-    const hb_cg_result &result(int i) const { return slots_[i].result; }
+    hb_cg_result result(int i) const
+    {
+        hb_cg_result r = slots_[i].result;
+        r.persistent_segments = slots_[i].psegments;
+        return r;
+    }
     void release(int i)
     {
         slots_[i] = Slot{};
-        dirty_ = true;
+        dirty_ = pdirty_ = true;
     }
 
     // Start a solve in slot i (enqueued; its first state is read at the next step).
@@ -139,7 +151,7 @@ class BatchRunner {
         P.use32 = mixed ? 1 : 0;
         P.inv = pc ? w.jinv : nullptr;
         q.rp.inv = P.inv;
-        dirty_ = true;
+        dirty_ = pdirty_ = true;
         return HB_OK;
     }
 
@@ -160,6 +172,7 @@ class BatchRunner {
             if (slots_[i].used && !slots_[i].finished) run.push_back(i);
         if (run.empty()) return HB_OK;
         max_quota = std::max(max_quota, 1);
+        if (persistent_ && persist_eligible(run)) return step_persistent(run, iters, max_quota);
         // the lists depend on the running set, the quotas and the schedule
         // table (tile counts and order): rebuilt when any of them changed
         if ((dirty_ || max_quota != built_quota_ || ax_schedule_epoch() != built_epoch_) &&
@@ -189,6 +202,7 @@ class BatchRunner {
         hb_cg_opts opts{};
         Replacer rp;
         hb_cg_result result{};
+        int psegments = 0;  // steps of this problem inside persistent launches
     };
     // Cumulative list length after the problems whose multiplier is >= mult.
     struct Level {
@@ -201,6 +215,126 @@ class BatchRunner {
         const void *D;              // the class's derivative matrix (any of its meshes)
         std::vector<Level> levels;  // items of the class's problems, by multiplier (descending)
     };
+    // The persistent launch takes problems of the degrees it is compiled for, on
+    // boxes of one kind (plain or Dirichlet), at most one per workgroup the
+    // device holds.
+    bool persist_eligible(const std::vector<int> &run) const
+    {
+        const int cap = persist_capacity();
+        if (cap == 0 || static_cast<int>(run.size()) > cap) return false;
+        for (int i : run) {
+            const BatchProb &P = h_probs_[i];
+            if (!persist_degree(P.N) || P.dirichlet != h_probs_[run.front()].dirichlet) return false;
+        }
+        return true;
+    }
+
+    // Per-problem bytes streamed by one iteration: operator (60 N_L FP64,
+    // 32 N_L FP32) plus vectors (~88 N_G).
+    double iteration_cost(int i) const
+    {
+        const BatchProb &P = h_probs_[i];
+        const double nl = static_cast<double>(P.E) * (P.N + 1) * (P.N + 1) * (P.N + 1);
+        return (P.use32 ? 32.0 : 60.0) * nl + 88.0 * static_cast<double>(P.NG);
+    }
+
+    // Quota multipliers (as build_lists) and the workgroups of each problem in
+    // the persistent launch: one each, the rest of the device's workgroups in
+    // proportion to the bytes each problem streams during the launch, each
+    // capped by its operator tiles and by its partial-sum arrays.
+    hb_status build_persist(const std::vector<int> &run, int max_quota)
+    {
+        HB_HIP(hipStreamSynchronize(s_));  // earlier launches may still read the tables
+        const int cap = persist_capacity();
+        if (!pwgs_) {
+            if (hipMalloc(&pwgs_, sizeof(PersistWg) * cap) != hipSuccess ||
+                hipMalloc(&pslots_, sizeof(PersistSlot) * cap_) != hipSuccess ||
+                hipMalloc(&pbar_, sizeof(uint32_t) * cap_ + sizeof(int32_t)) != hipSuccess ||
+                hipHostMalloc(&h_pwgs_, sizeof(PersistWg) * cap, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc(&h_pslots_, sizeof(PersistSlot) * cap_, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc(&h_perr_, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(HB_ERR_OUT_OF_MEMORY, "batch runner: persistent launch tables");
+            }
+        }
+        double wmax = 0.0, total = 0.0;
+        for (int i : run) wmax = std::max(wmax, iteration_cost(i));
+        mult_.assign(cap_, 1);
+        for (int i : run) {
+            int m = 1;
+            while (m * 2 <= max_quota && iteration_cost(i) * (m * 2) <= wmax) m *= 2;
+            mult_[i] = m;
+            total += iteration_cost(i) * m;
+        }
+        std::vector<int> nwg(cap_, 0), top(cap_, 0);
+        int used = 0;
+        for (int i : run) {
+            const BatchProb &P = h_probs_[i];
+            const int64_t vec_len = std::max<int64_t>(3 * vec_blocks(P.NG), 2 * ((P.NG + kBatchChunk - 1) / kBatchChunk));
+            const int64_t lanes = (P.NG + kPersistThreads - 1) / kPersistThreads;
+            top[i] = static_cast<int>(std::max<int64_t>(
+                1, std::min<int64_t>({persist_tiles(P.N, P.E), vec_len / 2, lanes})));
+            nwg[i] = 1;
+            ++used;
+        }
+        // the remaining workgroups, one at a time to the problem with the most bytes per workgroup
+        while (used < cap) {
+            int best = -1;
+            double best_load = 0.0;
+            for (int i : run) {
+                if (nwg[i] >= top[i]) continue;
+                const double load = iteration_cost(i) * mult_[i] / nwg[i];
+                if (load > best_load) {
+                    best_load = load;
+                    best = i;
+                }
+            }
+            if (best < 0) break;
+            ++nwg[best];
+            ++used;
+        }
+        int k = 0;
+        for (int i : run) {
+            const BatchProb &P = h_probs_[i];
+            PersistSlot &sl = h_pslots_[i];
+            sl.walk = persist_walk(P.N, P.nx, P.ny, P.nz);
+            sl.tiles = persist_tiles(P.N, P.E);
+            sl.nwg = nwg[i];
+            sl.iters = 0;
+            sl.pad = 0;
+            for (int r = 0; r < nwg[i]; ++r) h_pwgs_[k++] = PersistWg{i, r};
+        }
+        persist_nwg_ = k;
+        (void)total;
+        HB_HIP(hipMemcpyAsync(probs_, h_probs_, sizeof(BatchProb) * cap_, hipMemcpyHostToDevice, s_));
+        HB_HIP(hipMemcpyAsync(pwgs_, h_pwgs_, sizeof(PersistWg) * k, hipMemcpyHostToDevice, s_));
+        pquota_ = max_quota;
+        pdirty_ = false;
+        return HB_OK;
+    }
+
+    // One step as one persistent launch: every running problem advances
+    // `iters` iterations times its quota multiplier.
+    hb_status step_persistent(const std::vector<int> &run, int iters, int max_quota)
+    {
+        hb_status st;
+        if ((pdirty_ || max_quota != pquota_) && (st = build_persist(run, max_quota))) return st;
+        for (int i : run) h_pslots_[i].iters = iters * mult_[i];
+        HB_HIP(hipMemcpyAsync(pslots_, h_pslots_, sizeof(PersistSlot) * cap_, hipMemcpyHostToDevice, s_));
+        int32_t *err = reinterpret_cast<int32_t *>(pbar_ + cap_);
+        HB_HIP(hipMemsetAsync(pbar_, 0, sizeof(uint32_t) * cap_ + sizeof(int32_t), s_));
+        if ((st = launch_batch_persistent(h_probs_[run.front()].dirichlet != 0, pwgs_, persist_nwg_, pslots_, probs_,
+                                          pbar_, err, s_)))
+            return st;
+        HB_HIP(hipMemcpyAsync(h_perr_, err, sizeof(int32_t), hipMemcpyDeviceToHost, s_));
+        ++persist_steps_;
+        for (int i : run) ++slots_[i].psegments;
+        if ((st = handle_stops(run))) return st;  // synchronises the stream
+        if (*h_perr_)
+            return fail(HB_ERR_DEVICE, "persistent batch: a barrier among a problem's workgroups timed out");
+        return HB_OK;
+    }
+
     // The launches of one step: `iters` iterations of every running problem
     // (times its quota multiplier), on stream s.
     hb_status enqueue_step(int iters, hipStream_t s)
@@ -298,7 +432,7 @@ class BatchRunner {
                 q.finished = true;
             }
         }
-        dirty_ = true;
+        dirty_ = pdirty_ = true;
         return HB_OK;
     }
 
@@ -390,6 +524,7 @@ class BatchRunner {
         HB_HIP(hipMemcpyAsync(plist_, h_plist_, sizeof(int32_t) * nrun, hipMemcpyHostToDevice, s_));
         built_quota_ = max_quota;
         dirty_ = false;
+        pdirty_ = true;  // mult_ was rewritten
         return HB_OK;
     }
 
@@ -431,7 +566,7 @@ class BatchRunner {
             q.result.res = h_norms_[i];
             q.result.bnorm = std::sqrt(hs.bb);
             q.finished = true;
-            dirty_ = true;
+            dirty_ = pdirty_ = true;
         }
         for (int i : replaced) {
             Slot &q = slots_[i];
@@ -440,7 +575,7 @@ class BatchRunner {
             if (q.rp.finished) finish(i, h_states_[i].iters);
             if (was32 != q.rp.use32) {
                 h_probs_[i].use32 = q.rp.use32 ? 1 : 0;
-                dirty_ = true;
+                dirty_ = pdirty_ = true;
             }
         }
         return HB_OK;
@@ -451,7 +586,7 @@ class BatchRunner {
         Slot &q = slots_[i];
         q.rp.fill(&q.result, iters);
         q.finished = true;
-        dirty_ = true;
+        dirty_ = pdirty_ = true;
     }
 
     int cap_;
@@ -468,6 +603,14 @@ class BatchRunner {
     std::vector<int> mult_;
     int vec_off_ = 0, top_mult_ = 1, built_quota_ = 0, built_epoch_ = -1;
     bool dirty_ = true;
+    // persistent launches
+    bool persistent_ = false, pdirty_ = true;  // pdirty_: the persistent tables are stale
+    int pquota_ = 0;
+    PersistWg *pwgs_ = nullptr, *h_pwgs_ = nullptr;
+    PersistSlot *pslots_ = nullptr, *h_pslots_ = nullptr;
+    uint32_t *pbar_ = nullptr;  // a barrier counter per slot, then the error flag
+    int32_t *h_perr_ = nullptr;
+    int persist_nwg_ = 0, persist_steps_ = 0;
     // graph replay of steps
     bool graphs_ = false;
     hipStream_t cap_s_ = nullptr;
@@ -584,6 +727,7 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
         chunk = fixed ? std::min(chunk, opts->graph_k) : opts->graph_k;
         runner.use_graphs(true);
     }
+    runner.use_persistent(opts->persistent != 0);
     do {
         if ((st = runner.step(chunk))) return st;
     } while (runner.running() > 0);
