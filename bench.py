@@ -6,11 +6,13 @@ One step = the paper's operator protocol (50 back-to-back operator calls) plus
 one 100-iteration CG solve (the benchmark's fixed iteration count), all inputs
 resident in HBM.  After the timed steps (outside them): 64 uneven problems
 solved one by one in FP64 vs batched (FP64, and FP32 operator with FP64
-residual replacement), and the first arrivals of the serving trace through the
-continuous-batching engine vs one at a time in FP64, all to 1e-8 relative
-residual.  Prints one JSON line.
+residual replacement), and the serving recipe through the continuous-batching
+engine vs one at a time in FP64, all to 1e-8 relative residual: its first R
+arrivals, a 60 s window at 4 requests/s, and the configured 200 requests/s cut
+off after 20 s of wall time.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batch] [--serve-requests R]
+                  [--no-serve-window]
 """
 from __future__ import annotations
 
@@ -328,6 +330,32 @@ def served_vs_sequential(hb, torch, inputs, count, rtol=1e-8):
     return out
 
 
+def served_window_and_overload(hb, torch, inputs, rate=4.0, window=60.0, budget=20.0, rtol=1e-8):
+    """The serving recipe over its time window: (1) a 60 s window of arrivals at an
+    offered rate one GPU sustains with the engine, every request served to the end
+    (FP32 operator with FP64 residual replacement and the Jacobi preconditioner)
+    beside one at a time in FP64; (2) the configured 200 req/s trace, cut off after
+    `budget` seconds of wall time: requests completed, their latency, and the
+    backlog of arrived but unfinished ones."""
+    from paper_2202_12477_amd import serving
+
+    w = inputs.serving_window(window, rate)
+    win = {"offered_per_s": rate, "window_s": window, "requests": len(w), "hbm_budget_gb": 64}
+    win["engine_fp32rr_jacobi"] = serving.replay_engine(w, prec=hb.PREC_FP32_RR, rtol=rtol,
+                                                        precond=hb.PRECOND_JACOBI, progress=50)
+    print(f"# serving window engine: {win['engine_fp32rr_jacobi']}", file=sys.stderr, flush=True)
+    win["sequential_fp64"] = serving.replay_sequential(w, rtol=rtol, progress=50)
+    print(f"# serving window sequential: {win['sequential_fp64']}", file=sys.stderr, flush=True)
+    trace = inputs.serving_trace(int(200 * budget * 1.2) + 64)
+    over = {"offered_per_s": 200.0, "budget_s": budget, "hbm_budget_gb": 64}
+    over["engine_fp32rr_jacobi"] = serving.replay_engine(trace, prec=hb.PREC_FP32_RR, rtol=rtol,
+                                                         precond=hb.PRECOND_JACOBI, budget=budget)
+    print(f"# serving overload engine: {over['engine_fp32rr_jacobi']}", file=sys.stderr, flush=True)
+    over["sequential_fp64"] = serving.replay_sequential(trace, rtol=rtol, budget=budget)
+    print(f"# serving overload sequential: {over['sequential_fp64']}", file=sys.stderr, flush=True)
+    return {"window": win, "overload": over}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +367,8 @@ def main():
     ap.add_argument("--no-two-phase", action="store_true", help="skip the two-phase operator comparison")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="arrivals of the serving trace to replay (0 skips the serving comparison)")
+    ap.add_argument("--no-serve-window", action="store_true",
+                    help="skip the 60 s serving window and the 200 req/s overload run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the operator and CG of this library run on a single device "
@@ -439,6 +469,8 @@ def main():
         out["batch"] = batched_vs_sequential(hb, torch, inputs)
     if args.serve_requests > 0:
         out["serving"] = served_vs_sequential(hb, torch, inputs, args.serve_requests)
+    if not args.no_serve_window:
+        out["serving_window"] = served_window_and_overload(hb, torch, inputs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inputs.PLAIN_SMALL, case)
     print(json.dumps(out), flush=True)

@@ -80,6 +80,13 @@ def batched_cases(count: int = 64, master_seed: int = 4) -> list:
                     1000 * master_seed + i, 2000 * master_seed + i) for i, (n, N) in enumerate(zip(ns, Ns))]
 
 
+def serving_window(duration: float, rate: float, master_seed: int = 5) -> list:
+    """The arrivals of the serving recipe (serving_trace's request mix, its master
+    seed) within the first `duration` seconds at `rate` requests per second."""
+    count = int(rate * duration * 2 + 64)
+    return [(t, c) for t, c in serving_trace(count, rate, master_seed) if t <= duration]
+
+
 def serving_trace(count: int, rate: float = 200.0, master_seed: int = 5) -> list:
     """Request stream: Poisson arrivals at `rate` per second; each request is a
     near-cubic box whose element count E* is log-uniform in [8, 32768]

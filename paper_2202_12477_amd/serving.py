@@ -22,17 +22,29 @@ from . import HB_OK, PREC_FP64, Engine, Mesh, rhs_uniform
 def _summary(lat, wall, iters, extra=None):
     lat = np.asarray(lat)
     out = {"requests": int(lat.size), "wall_s": round(wall, 3), "solves_per_s": round(lat.size / wall, 3),
-           "p50_s": round(float(np.percentile(lat, 50)), 4), "p99_s": round(float(np.percentile(lat, 99)), 4),
-           "mean_s": round(float(lat.mean()), 4), "cg_iterations": int(iters)}
+           "p50_s": round(float(np.percentile(lat, 50)), 4) if lat.size else None,
+           "p99_s": round(float(np.percentile(lat, 99)), 4) if lat.size else None,
+           "mean_s": round(float(lat.mean()), 4) if lat.size else None, "cg_iterations": int(iters)}
     if extra:
         out.update(extra)
     return out
 
 
+def _budget_extra(trace, budget, wall, done):
+    """Counts of a run cut off after `budget` seconds (it ended at `wall`): requests
+    that had arrived by the cut-off, completed, and left unfinished (queued or
+    running), and the completion rate over the budget."""
+    offered = sum(1 for arrival, _ in trace if arrival <= min(budget, wall))
+    return {"budget_s": budget, "offered": offered, "completed": done, "backlog": offered - done,
+            "completed_per_s": round(done / budget, 3)}
+
+
 def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, iters_per_step=25,
-                  max_iter=200000, precond=0, progress=None):
+                  max_iter=200000, precond=0, progress=None, budget=None):
     """Submit each request when its arrival time has passed, step the engine while
-    anything is queued or running, and poll for completions after every step."""
+    anything is queued or running, and poll for completions after every step.
+    With `budget` (seconds) the loop stops at that wall time: the summary covers the
+    requests completed by then and counts those offered and left unfinished."""
     import torch
 
     eng = Engine(hbm_budget, max_slots=max_slots, prec=prec, max_iter=max_iter, iters_per_step=iters_per_step,
@@ -43,6 +55,8 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
         nxt, lat, iters, steps, waiting = 0, [], 0, 0, {}
         while len(lat) < len(trace):
             now = time.perf_counter() - t0
+            if budget is not None and now >= budget:
+                break
             while nxt < len(trace) and trace[nxt][0] <= now:
                 arrival, c = trace[nxt]
                 t = eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, rhs_seed=c.rhs_seed,
@@ -50,14 +64,20 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
                 waiting[t] = arrival
                 nxt += 1
             if not waiting:
-                time.sleep(max(0.0, trace[nxt][0] - (time.perf_counter() - t0)))
+                pause = trace[nxt][0] - (time.perf_counter() - t0)
+                if budget is not None:
+                    pause = min(pause, budget - (time.perf_counter() - t0))
+                time.sleep(max(0.0, pause))
                 continue
-            eng.step()
+            ready = eng.step()["completed"]  # results waiting to be polled
             steps += 1
             for t in list(waiting):
+                if ready == 0:
+                    break
                 got = eng.poll(t, want_x=False)
                 if got is None:
                     continue
+                ready -= 1
                 res = got[0]
                 if res.status != HB_OK:
                     raise RuntimeError(f"request {t} ended with status {res.status}")
@@ -69,12 +89,16 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
         wall = time.perf_counter() - t0
     finally:
         eng.close()
-    return _summary(lat, wall, iters, {"engine_steps": steps})
+    extra = {"engine_steps": steps}
+    if budget is not None:
+        extra.update(_budget_extra(trace, budget, wall, len(lat)))
+    return _summary(lat, wall, iters, extra)
 
 
-def replay_sequential(trace, *, rtol=1e-8, max_iter=200000, progress=None):
+def replay_sequential(trace, *, rtol=1e-8, max_iter=200000, progress=None, budget=None):
     """One request at a time in arrival order, FP64 CG (hb_cg_solve), the solution
-    copied to the host like the engine's retirement does."""
+    copied to the host like the engine's retirement does.  With `budget` (seconds)
+    no request starts after that wall time (the one running then completes)."""
     import torch
 
     torch.cuda.synchronize()
@@ -82,6 +106,8 @@ def replay_sequential(trace, *, rtol=1e-8, max_iter=200000, progress=None):
     lat, iters = [], 0
     for arrival, c in trace:
         now = time.perf_counter() - t0
+        if budget is not None and (now >= budget or arrival >= budget):
+            break
         if now < arrival:
             time.sleep(arrival - now)
         m = Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
@@ -100,4 +126,8 @@ def replay_sequential(trace, *, rtol=1e-8, max_iter=200000, progress=None):
         if progress and len(lat) % progress == 0:
             print(f"  sequential: {len(lat)}/{len(trace)} done at {time.perf_counter() - t0:.1f} s",
                   file=sys.stderr, flush=True)
-    return _summary(lat, time.perf_counter() - t0, iters)
+    wall = time.perf_counter() - t0
+    extra = None
+    if budget is not None:
+        extra = _budget_extra(trace, budget, wall, len(lat))
+    return _summary(lat, wall, iters, extra)
