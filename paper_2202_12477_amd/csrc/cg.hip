@@ -289,11 +289,20 @@ int vec_blocks(int64_t n)
     return static_cast<int>(want < 1 ? 1 : (want > 2048 ? 2048 : want));
 }
 
+// Clearing takes one entry per thread and up to 32768 workgroups: a store-only
+// kernel needs many more stores in flight than the vector kernels' 2048-workgroup
+// grid gives (the 32^3 N=7 vector: 15.7 us against 18.4 us with 2048 workgroups).
+inline int zero_blocks(int64_t n)
+{
+    const int64_t want = (n + kVecThreads - 1) / kVecThreads;
+    return static_cast<int>(want < 1 ? 1 : (want > 32768 ? 32768 : want));
+}
+
 template <typename V>
 hb_status zero_any(V *v, int64_t n, hipStream_t s)
 {
     if (n == 0) return HB_OK;
-    zero_kernel<V><<<vec_blocks(n), kVecThreads, 0, s>>>(v, n);
+    zero_kernel<V><<<zero_blocks(n), kVecThreads, 0, s>>>(v, n);
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
