@@ -343,12 +343,16 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 
 /* ------------------------------------------------------------------------ */
 /* Operator tile schedules and their autotuner.                              */
-/* The operator (single, CG and batched launches) runs one of four compiled */
+/* The operator (single, CG and batched launches) runs one of the compiled  */
 /* tile schedules per (degree, precision) class: bit 0 (1) reads the        */
 /* columns of D for the divergence from LDS instead of registers; bit 1 (2)  */
 /* uses one-wave workgroups instead of 256-thread workgroups (N <= 7, where  */
 /* an element fits in a wave); bit 2 (4) keeps no f_t array and targets two  */
-/* waves per SIMD (N >= 8).  The choice changes the reduction grouping of    */
+/* waves per SIMD (N >= 8); bit 3 (8, N = 7 only, not with bit 1) gives a    */
+/* 256-thread workgroup four x-consecutive elements, one per wave, sums      */
+/* their shared faces in LDS and assembles each row of 4N+1 DOFs once       */
+/* (where 4 does not divide nx, each row of the box ends in a shorter tile). */
+/* Schedule values are 0..15.  The choice changes the reduction grouping of  */
 /* p.Ap, the order of assembly atomics and of the t-part sums only (results  */
 /* agree to rounding).  The table is process-wide, starts from measured      */
 /* defaults, and must not be changed while solves are in flight.  `prec`:    */
@@ -358,7 +362,7 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 typedef struct {
     int32_t schedule;   /* the schedule chosen (now in the table) */
     int32_t candidates; /* schedules timed */
-    double us[8];       /* mean launch time per schedule value in microseconds; < 0: not available here */
+    double us[16];      /* mean launch time per schedule value in microseconds; < 0: not available here */
 } hb_tune_result;
 
 /* Current schedule of a class. */

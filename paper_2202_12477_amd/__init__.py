@@ -87,7 +87,7 @@ class _CgResult(ctypes.Structure):
 
 
 class _TuneResult(ctypes.Structure):
-    _fields_ = [("schedule", ctypes.c_int32), ("candidates", ctypes.c_int32), ("us", ctypes.c_double * 8)]
+    _fields_ = [("schedule", ctypes.c_int32), ("candidates", ctypes.c_int32), ("us", ctypes.c_double * 16)]
 
 
 _lib = None
@@ -419,6 +419,7 @@ def rhs_uniform(b, seed: int, stream=None):
 SCHED_COLS_LDS = 1
 SCHED_WAVE = 2
 SCHED_LEAN = 4
+SCHED_MERGE = 8
 
 
 def get_schedule(N: int, prec: int = PREC_FP64) -> int:
@@ -439,7 +440,7 @@ def autotune(N: int, prec: int = PREC_FP64, local_nodes: int = 0, reps: int = 20
     r = _TuneResult()
     _check(lib().hb_autotune(N, prec, local_nodes, reps, ctypes.byref(r), _stream(stream)), "hb_autotune")
     return {"N": N, "prec": prec, "schedule": r.schedule, "candidates": r.candidates,
-            "us": {v: round(r.us[v], 2) for v in range(8) if r.us[v] >= 0}}
+            "us": {v: round(r.us[v], 2) for v in range(16) if r.us[v] >= 0}}
 
 
 def stream_probe(inp, out, stream=None):

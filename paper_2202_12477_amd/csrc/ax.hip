@@ -19,8 +19,8 @@ namespace hb {
     hb_status launch_ax32_d_##n(const hb_mesh_s *, double, const double *, float *, double *, CgState *,        \
                                 hipStream_t);                                                                   \
     hb_status launch_batch_ax_d_##n(const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t); \
-    int ax_grid_##n(int64_t, int);                                                                              \
-    int ax_epb_##n(int);
+    int ax_epb_##n(int);                                                                                        \
+    TileWalk ax_walk_##n(int64_t, int64_t, int64_t, int);
 HB_DECL_AX(1) HB_DECL_AX(2) HB_DECL_AX(3) HB_DECL_AX(4) HB_DECL_AX(5) HB_DECL_AX(6) HB_DECL_AX(7) HB_DECL_AX(8)
 HB_DECL_AX(9) HB_DECL_AX(10) HB_DECL_AX(11) HB_DECL_AX(12) HB_DECL_AX(13) HB_DECL_AX(14) HB_DECL_AX(15)
 #undef HB_DECL_AX
@@ -30,13 +30,14 @@ HB_DECL_AX(9) HB_DECL_AX(10) HB_DECL_AX(11) HB_DECL_AX(12) HB_DECL_AX(13) HB_DEC
 namespace {
 
 // Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups, N <= 7;
-// bit 2: lean registers with two waves per SIMD, N >= 8): the autotuner's
-// choices on this part at about 2^24 local nodes per degree (the order-sweep
-// size), kept where the winner beat the plain schedule by more than ~1.5%.
+// bit 2: lean registers with two waves per SIMD, N >= 8; bit 3: merged row
+// assembly, N = 7): the autotuner's choices on this part at about 2^24 local
+// nodes per degree (the order-sweep size), kept where the winner beat the plain
+// schedule by more than ~1.5%.
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 1, 3, 1, 3, 0, 0, 3, 0, 0, 0, 1, 4, 5, 5, 5},  // FP64
-    {0, 0, 3, 0, 0, 1, 0, 2, 0, 1, 1, 0, 0, 0, 1, 0},  // FP32
+    {0, 1, 3, 1, 3, 0, 0, 9, 0, 0, 0, 1, 4, 5, 5, 5},  // FP64
+    {0, 0, 3, 0, 0, 1, 0, 8, 0, 1, 1, 0, 0, 0, 1, 0},  // FP32
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};
@@ -63,8 +64,9 @@ int ax_schedule(int N, bool fp32)
 bool ax_schedule_legal(int N, int v)
 {
     const bool small = (N + 1) * (N + 1) <= 64;  // an element fits in a wave
+    const bool wave = (N + 1) * (N + 1) == 64;   // an element is exactly a wave
     return N >= 1 && N <= kMaxN && v >= 0 && v < kNumSched && (!(v & kSchedWave) || small) &&
-           (!(v & kSchedLean) || !small);
+           (!(v & kSchedLean) || !small) && (!(v & kSchedMerge) || (wave && !(v & kSchedWave)));
 }
 
 void set_ax_schedule(int N, bool fp32, int v)
@@ -120,39 +122,45 @@ hb_status launch_batch_ax(int N, const void *D, bool fp32, bool dirichlet, const
     }
 }
 
-int ax_grid_for(int N, int64_t E, int sched)
-{
-    switch (N) {
-#define HB_CASE(n) \
-    case n: return ax_grid_##n(E, sched);
-        HB_ALL_N(HB_CASE)
-#undef HB_CASE
-    default: return 0;
-    }
-}
-
 TileWalk ax_walk_for(int N, int64_t nx, int64_t ny, int64_t nz, int sched)
 {
     switch (N) {
 #define HB_CASE(n) \
-    case n: return make_walk(nx, ny, nz, ax_epb_##n(sched));
+    case n: return ax_walk_##n(nx, ny, nz, sched);
         HB_ALL_N(HB_CASE)
 #undef HB_CASE
     default: return TileWalk{};
     }
 }
 
+int ax_epb_for(int N, int sched)
+{
+    switch (N) {
+#define HB_CASE(n) \
+    case n: return ax_epb_##n(sched);
+        HB_ALL_N(HB_CASE)
+#undef HB_CASE
+    default: return 1;
+    }
+}
+
+int ax_grid_for(int N, int64_t E, int64_t nx, int64_t ny, int64_t nz, int sched)
+{
+    return static_cast<int>(walk_tiles(ax_walk_for(N, nx, ny, nz, sched), E, ax_epb_for(N, sched)));
+}
+
 int ax_blocks(const hb_mesh_s *m, bool fp32)
 {
     if (!fp32 && (m->desc.flags & HB_MESH_GATHER)) return ax_local_blocks(m);
-    return ax_grid_for(m->N, m->E, ax_schedule(m->N, fp32));
+    return ax_grid_for(m->N, m->E, m->desc.nx, m->desc.ny, m->desc.nz, ax_schedule(m->N, fp32));
 }
 
 int ax_blocks_max(const hb_mesh_s *m)
 {
     int g = 0;
     for (int v = 0; v < kNumSched; ++v)
-        if (ax_schedule_legal(m->N, v)) g = std::max(g, ax_grid_for(m->N, m->E, v));
+        if (ax_schedule_legal(m->N, v))
+            g = std::max(g, ax_grid_for(m->N, m->E, m->desc.nx, m->desc.ny, m->desc.nz, v));
     return g;
 }
 

@@ -64,6 +64,20 @@ template <int N>
 constexpr bool kWaveLegal = (N + 1) * (N + 1) <= 64;
 template <int N>
 constexpr bool kLeanLegal = !kWaveLegal<N>;
+//   kSchedMerge   - (N = 7, where an element is exactly one wave) a 256-thread
+//                   workgroup holds four x-consecutive elements, one per wave,
+//                   whose layer loops synchronise within their wave only; at
+//                   the end the workgroup sums the three faces the elements
+//                   share in LDS and assembles each of the tile's (N+1)^2 rows
+//                   of 4N+1 consecutive DOFs once.  Each atomic add is a
+//                   read-modify-write at the memory side on this part, and a
+//                   row of 29 DOFs goes out in fewer, fuller requests than four
+//                   rows of 8.
+template <int N>
+constexpr bool kMergeLegal = (N + 1) * (N + 1) == 64;
+// the merged schedule's tiles lie in one row of the box, so its walk pads the rows
+template <int N, int V>
+constexpr bool kPadRows = (V & kSchedMerge) != 0 && kMergeLegal<N>;
 
 template <int N, int V = 0>
 struct AxShape {
@@ -111,17 +125,19 @@ __device__ inline void atomic_add(gptr<T> p, T v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One tile of EPB elements starting at element tile*EPB: y += A x on them and,
+// One tile of up to EPB consecutive elements (sp.e0 .. sp.e0 + sp.n - 1): y += A x on them and,
 // with DOT, this block's sum of x_e . y_e, returned in every thread and written
 // to *dot_out (thread 0) unless dot_out is null.
 // Every thread of the block must call it (it synchronises the block).
 // (Always inlined: the single-problem and the batched kernel both call it, and
 // an out-of-line call would spill the whole register set.)
+// rows: the tile's elements are x-consecutive in one row of the box (the
+// merged assembly needs it; without it that schedule assembles node by node).
 template <int N, bool DOT, typename T, int V, bool MASK, bool LOCAL = false>
-__device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64_t tile, gptr<const int32_t> __restrict__ map,
+__device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gptr<const int32_t> __restrict__ map,
                                gptr<const T> __restrict__ geo, gptr<const T> __restrict__ Dm, T lambda,
                                gptr<const double> __restrict__ x, gptr<T> __restrict__ y,
-                               gptr<double> __restrict__ dot_out)
+                               gptr<double> __restrict__ dot_out, bool rows = false)
 {
     using S = AxShape<N, V>;
     constexpr int n1 = S::n1, np2 = S::np2, np3 = S::np3, epb = S::epb;
@@ -145,9 +161,8 @@ __device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64
     const int el = lane_used ? t / np2 : epb - 1;  // spare lanes mirror the last element, inactive
     const int ab = lane_used ? t - el * np2 : 0;
     const int a = ab % n1, b = ab / n1;
-    const int64_t e = tile * epb + el;
-    const bool active = lane_used && (e < E);
-    const int64_t eo = e < E ? e : E - 1;  // inactive lanes read a valid element and discard it
+    const bool active = lane_used && el < sp.n;
+    const int64_t eo = sp.e0 + (el < sp.n ? el : sp.n - 1);  // inactive lanes read a valid element and discard it
     // rows a, b of D in registers, loaded once; columns a, b likewise, or D^T in LDS
     constexpr bool cols_lds = (V & kSchedColsLds) != 0;
     __shared__ T sDt[cols_lds ? np2 : 1];
@@ -161,9 +176,22 @@ __device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64
             DbT[m] = Dm[m * n1 + b];
         }
     }
+    // merged assembly: each wave holds one element and its own LDS slices, so the
+    // layer loop synchronises within the wave (LDS writes complete before the reads)
+    constexpr bool merge = (V & kSchedMerge) != 0 && kMergeLegal<N> && !LOCAL;
+    auto layer_sync = [] {
+        if constexpr (merge) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        } else {
+            __syncthreads();
+        }
+    };
     if constexpr (cols_lds) {
         // sDt[i][m] = D[m][i]; the first layer's barriers order these stores before any read
         for (int i = t; i < np2; i += S::threads) sDt[(i % n1) * n1 + i / n1] = Dm[i];
+        if constexpr (merge) __syncthreads();  // filled by the first wave, read by all
     }
 
     // gather through Z: the (a,b) column of the element
@@ -215,7 +243,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64
     }
     if constexpr (pipe) {
         if (lane_used) sq[0][el][ab] = q[0];
-        __syncthreads();
+        layer_sync();
     }
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
@@ -237,7 +265,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64
         for (int m = 0; m < n1; ++m) qt += Dm[c * n1 + m] * q[m];
         if constexpr (!pipe) {
             if (lane_used) sq[0][el][ab] = q[c];
-            __syncthreads();
+            layer_sync();
         }
         T qr = 0, qs = 0;
 #pragma unroll
@@ -262,7 +290,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64
             ss[cb][el][ab] = fs;
             if (pipe && c + 1 < n1) sq[cb ^ 1][el][ab] = q[c + 1];
         }
-        __syncthreads();
+        layer_sync();
         if constexpr (sizeof(T) == 8) {
             // FP64: the r half, then the s half.  Issued together, the two
             // halves' LDS operands are the register peak of the kernel (at N=7
@@ -320,6 +348,44 @@ __device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64
             for (int c = 0; c < n1; ++c) yl[c * np2] = yv[c];
         }
     } else {
+    bool assembled = false;
+    if constexpr (merge) {
+        if (rows) {
+            // the tile's (N+1)^2 rows of n N + 1 DOFs (n = sp.n elements): every
+            // element stores its a < N nodes (the last one also a = N), then the
+            // a = N nodes of the others are added to the a = 0 nodes of their right
+            // neighbours, then each row goes out as one run of atomic adds (the
+            // indices come from the lanes' own map entries; a shared face's two
+            // copies agree)
+            static_assert(epb == 4 && S::threads == 4 * np2, "one element per wave, four per workgroup");
+            constexpr int L = epb * N + 1;
+            __shared__ T sy[n1][n1][L];
+            __shared__ uint32_t sid[n1][n1][L];
+            const int last = sp.n - 1;
+            if (active && (a < N || el == last)) {
+#pragma unroll
+                for (int c = 0; c < n1; ++c) {
+                    sy[c][b][N * el + a] = yv[c];
+                    sid[c][b][N * el + a] = idx[c];
+                }
+            }
+            __syncthreads();
+            if (a == N && el < last) {
+#pragma unroll
+                for (int c = 0; c < n1; ++c) sy[c][b][N * el + N] += yv[c];
+            }
+            __syncthreads();
+            const T *flat_y = &sy[0][0][0];
+            const uint32_t *flat_i = &sid[0][0][0];
+            const int used = N * sp.n + 1;  // entries of a row that a short tile fills
+            for (int k = t; k < n1 * n1 * L; k += S::threads) {
+                const uint32_t id = flat_i[k];
+                if ((sp.n == epb || k % L < used) && (!MASK || id != kNoDof)) atomic_add(&y[id], flat_y[k]);
+            }
+            assembled = true;
+        }
+    }
+    if (!assembled) {
     // assemble through Z^T.  Where several elements share a wave, the a = 0 face
     // node of an element is the a = N face node of the previous one whenever the
     // two are neighbours along r: the lanes holding them then see the same index,
@@ -356,6 +422,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(int64_t E, int64
         }
     }
     }
+    }
     if constexpr (DOT) {
         // sum_e x_e . y_e = x . Z^T y_L = x . A x, accumulated in FP64
         double v = 0.0;
@@ -381,8 +448,11 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
         // stopped, or stopping at the next alpha step (which reads no partials)
         if (st->done | st->pending) return;
     }
-    ax_tile<N, DOT, T, V, MASK>(E, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), to_global(map), to_global(geo), to_global(Dm),
-                          lambda, to_global(x), to_global(y), to_global(DOT ? partial + blockIdx.x : partial));
+    // rows: the walk is defined (whole or padded rows), so every tile is
+    // x-consecutive elements of one row
+    const TileSpan sp = tile_span(walk, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), E, AxShape<N, V>::epb);
+    ax_tile<N, DOT, T, V, MASK>(sp, to_global(map), to_global(geo), to_global(Dm), lambda, to_global(x),
+                                to_global(y), to_global(DOT ? partial + blockIdx.x : partial), walk.txn != 0);
 }
 
 // First phase of the two-phase operator: y_L = (S_L + lambda C) Z x per element
@@ -397,7 +467,8 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_local_ker
     if constexpr (DOT) {
         if (st->done | st->pending) return;
     }
-    ax_tile<N, DOT, double, V, MASK, true>(E, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), to_global(map),
+    const TileSpan sp = tile_span(walk, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), E, AxShape<N, V>::epb);
+    ax_tile<N, DOT, double, V, MASK, true>(sp, to_global(map),
                                            to_global(geo), to_global(Dm), lambda, to_global(x), to_global(yl),
                                            to_global(DOT ? partial + blockIdx.x : partial));
 }
@@ -443,12 +514,19 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void batch_ax_ker
     const auto map = to_global(uniform(P.map));
     const auto x = to_global(uniform(P.p));
     const auto part = to_global(uniform(P.part_ax) + tile);
+    // the list holds tiles of the same walk as the single-problem launch (padded
+    // rows under the merged schedule); with whole or padded rows a tile lies in one x-row
+    constexpr int epb = AxShape<N, V>::epb;
+    const int32_t nx = uniform(P.nx);
+    const TileWalk w = make_walk(nx, 1, 1, epb, kPadRows<N, V>);
+    const TileSpan sp = tile_span(w, static_cast<uint32_t>(tile), E, epb);
+    const bool rows = nx > 0 && w.txn != 0;
     if constexpr (sizeof(T) == 4)
-        ax_tile<N, true, float, V, MASK>(E, tile, map, to_global(uniform(P.geo32)), to_global(Dm),
-                                   static_cast<float>(uniform(P.lambda)), x, to_global(uniform(P.Ap32)), part);
+        ax_tile<N, true, float, V, MASK>(sp, map, to_global(uniform(P.geo32)), to_global(Dm),
+                                   static_cast<float>(uniform(P.lambda)), x, to_global(uniform(P.Ap32)), part, rows);
     else
-        ax_tile<N, true, double, V, MASK>(E, tile, map, to_global(uniform(P.geo)), to_global(Dm), uniform(P.lambda), x,
-                                    to_global(uniform(P.Ap)), part);
+        ax_tile<N, true, double, V, MASK>(sp, map, to_global(uniform(P.geo)), to_global(Dm), uniform(P.lambda), x,
+                                    to_global(uniform(P.Ap)), part, rows);
 }
 
 template <int N, int V>
@@ -457,13 +535,22 @@ int ax_grid(int64_t E)
     return static_cast<int>((E + AxShape<N, V>::epb - 1) / AxShape<N, V>::epb);
 }
 
+// The tile order of a box under schedule V, and its tile count.
+template <int N, int V>
+TileWalk ax_walk(int64_t nx, int64_t ny, int64_t nz)
+{
+    return make_walk(nx, ny, nz, AxShape<N, V>::epb, kPadRows<N, V>);
+}
+
 // Run-time schedule -> compile-time instantiation.  Bits not available at
 // this degree are dropped (the host validates schedules before they reach
 // the table, so this only bounds the instantiations).
 template <int N>
 constexpr int legal_sched(int v)
 {
-    return v & (kSchedColsLds | (kWaveLegal<N> ? kSchedWave : 0) | (kLeanLegal<N> ? kSchedLean : 0));
+    // merging needs the 256-thread tile: it drops the one-wave bit
+    const int m = v & (kMergeLegal<N> ? kSchedMerge : 0);
+    return (v & (kSchedColsLds | (kWaveLegal<N> && !m ? kSchedWave : 0) | (kLeanLegal<N> ? kSchedLean : 0))) | m;
 }
 template <int N, typename F>
 decltype(auto) with_schedule(int v, F &&f)
@@ -474,14 +561,10 @@ decltype(auto) with_schedule(int v, F &&f)
     case 3: return f(std::integral_constant<int, legal_sched<N>(3)>{});
     case 4: return f(std::integral_constant<int, legal_sched<N>(4)>{});
     case 5: return f(std::integral_constant<int, legal_sched<N>(5)>{});
+    case 8: return f(std::integral_constant<int, legal_sched<N>(8)>{});
+    case 9: return f(std::integral_constant<int, legal_sched<N>(9)>{});
     default: return f(std::integral_constant<int, 0>{});
     }
-}
-
-template <int N>
-int ax_grid_sched(int64_t E, int v)
-{
-    return with_schedule<N>(v, [&](auto VV) { return ax_grid<N, decltype(VV)::value>(E); });
 }
 
 template <int N>
@@ -490,16 +573,22 @@ int ax_epb_sched(int v)
     return with_schedule<N>(v, [&](auto VV) { return AxShape<N, decltype(VV)::value>::epb; });
 }
 
+template <int N>
+TileWalk ax_walk_sched(int64_t nx, int64_t ny, int64_t nz, int v)
+{
+    return with_schedule<N>(v, [&](auto VV) { return ax_walk<N, decltype(VV)::value>(nx, ny, nz); });
+}
+
 template <int N, typename T, bool MASK>
 hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambda, const double *x, T *y,
                       double *partial, CgState *st, hipStream_t s)
 {
     return with_schedule<N>(ax_schedule(N, sizeof(T) == 4), [&](auto VV) -> hb_status {
         constexpr int V = decltype(VV)::value;
-        const int grid = ax_grid<N, V>(m->E);
+        const TileWalk walk = ax_walk<N, V>(m->desc.nx, m->desc.ny, m->desc.nz);
+        const int grid = static_cast<int>(walk_tiles(walk, m->E, AxShape<N, V>::epb));
         if (grid == 0) return HB_OK;
         const T lam = static_cast<T>(lambda);
-        const TileWalk walk = make_walk(m->desc.nx, m->desc.ny, m->desc.nz, AxShape<N, V>::epb);
         if (st)
             ax_kernel<N, true, T, V, MASK><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
                                                                              y, partial, st);
@@ -570,8 +659,8 @@ hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int
     {                                                                                                          \
         return launch_batch_ax_n<n, false>(D, fp32, it, ni, pr, s);                                            \
     }                                                                                                          \
-    int ax_grid_##n(int64_t E, int v) { return ax_grid_sched<n>(E, v); }                                       \
     int ax_epb_##n(int v) { return ax_epb_sched<n>(v); }                                                       \
+    TileWalk ax_walk_##n(int64_t nx, int64_t ny, int64_t nz, int v) { return ax_walk_sched<n>(nx, ny, nz, v); }\
     }
 
 // The same entry points for Dirichlet boxes (boundary nodes without DOFs:

@@ -15,8 +15,9 @@ namespace hb {
 
 constexpr int kMaxN = 15;
 // Operator tile schedules (bit flags): D^T read from LDS; one-wave workgroups
-// (N <= 7); lean registers with two waves per SIMD (N >= 8).
-constexpr int kSchedColsLds = 1, kSchedWave = 2, kSchedLean = 4, kNumSched = 8;
+// (N <= 7); lean registers with two waves per SIMD (N >= 8); assembly of four
+// x-consecutive elements merged in LDS (N = 7: an element is one wave).
+constexpr int kSchedColsLds = 1, kSchedWave = 2, kSchedLean = 4, kSchedMerge = 8, kNumSched = 16;
 constexpr int kGeo = 7;  // G_rr, G_rs, G_rt, G_ss, G_st, G_tt, c
 
 // Thread-local error message behind hb_last_error().
@@ -202,7 +203,8 @@ hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float 
 // and the given precision; the largest over all schedules (sizes partials).
 int ax_blocks(const hb_mesh_s *m, bool fp32);
 int ax_blocks_max(const hb_mesh_s *m);
-int ax_grid_for(int N, int64_t E, int sched);
+// Operator tiles of a box of E = nx*ny*nz elements under a schedule (padded rows included).
+int ax_grid_for(int N, int64_t E, int64_t nx, int64_t ny, int64_t nz, int sched);
 // The order of the operator's tiles on an nx x ny x nz box under a schedule.
 TileWalk ax_walk_for(int N, int64_t nx, int64_t ny, int64_t nz, int sched);
 // Schedule table (per degree and precision), shared by every solve path.

@@ -469,7 +469,7 @@ class BatchRunner {
         // (sets the list lengths, so before sizing the lists)
         for (int i : run) {
             BatchProb &P = h_probs_[i];
-            P.ax_tiles = ax_grid_for(P.N, P.E, ax_schedule(P.N, P.use32 != 0));
+            P.ax_tiles = ax_grid_for(P.N, P.E, P.nx, P.ny, P.nz, ax_schedule(P.N, P.use32 != 0));
         }
         size_t need = 0;
         for (int i : run) need += h_probs_[i].ax_tiles + h_probs_[i].vec_chunks;

@@ -86,8 +86,9 @@ __device__ __attribute__((always_inline)) inline double operator_tiles(
 {
     double dot = 0.0;
     for (int i = rank; i < tiles; i += nwg)
-        dot += ax_tile<N, true, T, kPV<N>, MASK>(E, walk_tile(walk, static_cast<uint32_t>(i)), map, geo, D, lam, x, y,
-                                                 nullptr);
+        dot += ax_tile<N, true, T, kPV<N>, MASK>(
+            tile_span(walk, walk_tile(walk, static_cast<uint32_t>(i)), E, AxShape<N, kPV<N>>::epb), map, geo, D, lam,
+            x, y, nullptr);
     return dot;
 }
 

@@ -13,6 +13,10 @@
 // z-neighbour comes nx*ny elements later, after the lines have been evicted and
 // written back: the written bytes of y doubled.)
 //
+// With padded rows (the merged-assembly schedule, whose tiles must lie in one
+// row) a row of nx elements holds txn = ceil(nx/epb) tiles, the last one short,
+// so tiles never straddle rows whatever nx is.
+//
 // Plain constexpr arithmetic, so host code (list building, tests) and device
 // code evaluate the same function.
 #pragma once
@@ -23,6 +27,7 @@ namespace hb {
 
 struct TileWalk {
     uint32_t txn = 0, ny = 0, nz = 0, ys = 0;  // txn == 0: identity (plain element order)
+    uint32_t rowlen = 0;  // nonzero: padded rows of rowlen elements (txn tiles each, the last short)
 };
 
 // The j-th tile of the walk, 0 <= j < txn*ny*nz.
@@ -43,16 +48,45 @@ constexpr uint32_t walk_tile(const TileWalk &w, uint32_t j)
 }
 
 // The walk for a box of nx x ny x nz elements cut into tiles of epb elements;
-// identity where a tile would straddle two rows.
-constexpr TileWalk make_walk(int64_t nx, int64_t ny, int64_t nz, int epb)
+// where a tile would straddle two rows: padded rows if pad, else identity.
+constexpr TileWalk make_walk(int64_t nx, int64_t ny, int64_t nz, int epb, bool pad = false)
 {
     TileWalk w;
-    if (epb < 1 || nx % epb != 0) return w;
-    w.txn = static_cast<uint32_t>(nx / epb);
+    if (epb < 1 || nx < 0) return w;
+    if (nx % epb != 0) {
+        if (!pad) return w;
+        w.rowlen = static_cast<uint32_t>(nx);
+    }
+    w.txn = static_cast<uint32_t>((nx + epb - 1) / epb);
     w.ny = static_cast<uint32_t>(ny);
     w.nz = static_cast<uint32_t>(nz);
     w.ys = static_cast<uint32_t>((ny + 7) / 8);  // one slab per XCD
     return w;
+}
+
+// Tiles of a launch over E elements.
+constexpr int64_t walk_tiles(const TileWalk &w, int64_t E, int epb)
+{
+    return w.txn ? static_cast<int64_t>(w.txn) * w.ny * w.nz : (E + epb - 1) / epb;
+}
+
+// The elements of tile t (a value of walk_tile): e0 .. e0 + n - 1, n >= 1.
+struct TileSpan {
+    int64_t e0;
+    int32_t n;
+};
+constexpr TileSpan tile_span(const TileWalk &w, uint32_t t, int64_t E, int epb)
+{
+    if (w.rowlen) {
+        const uint32_t row = t / w.txn;
+        const uint32_t k = (t - row * w.txn) * static_cast<uint32_t>(epb);  // offset in the row
+        const uint32_t left = w.rowlen - k;
+        return TileSpan{static_cast<int64_t>(row) * w.rowlen + k,
+                        static_cast<int32_t>(left < static_cast<uint32_t>(epb) ? left : static_cast<uint32_t>(epb))};
+    }
+    const int64_t e0 = static_cast<int64_t>(t) * epb;
+    const int64_t left = E - e0;
+    return TileSpan{e0, static_cast<int32_t>(left < epb ? left : epb)};
 }
 
 }  // namespace hb

@@ -139,8 +139,8 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
     # measured defaults (autotuner at 2^24 local nodes), D^T from LDS for FP64 N = 11..14
-    fp64 = [1, 3, 1, 3, 0, 0, 3, 0, 0, 0, 1, 4, 5, 5, 5]
-    fp32 = [0, 3, 0, 0, 1, 0, 2, 0, 1, 1, 0, 0, 0, 1, 0]
+    fp64 = [1, 3, 1, 3, 0, 0, 9, 0, 0, 0, 1, 4, 5, 5, 5]
+    fp32 = [0, 3, 0, 0, 1, 0, 8, 0, 1, 1, 0, 0, 0, 1, 0]
     for N in range(1, 16):
         assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
         assert hb.get_schedule(N, hb.PREC_FP32_RR) == fp32[N - 1]
@@ -151,12 +151,20 @@ def test_schedule_table_validation(L):
     assert hb.get_schedule(8, hb.PREC_FP64) == 5
     hb.set_schedule(8, hb.PREC_FP64, before8)
     assert L.hb_set_schedule(7, 0, hb.SCHED_LEAN) == hb.HB_ERR_INVALID_ARG  # lean registers: N >= 8 only
-    assert L.hb_set_schedule(8, 0, 8) == hb.HB_ERR_INVALID_ARG
+    # merged assembly: N = 7 only (an element is one wave), not with one-wave workgroups
+    assert L.hb_set_schedule(8, 0, hb.SCHED_MERGE) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(3, 0, hb.SCHED_MERGE) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(7, 0, hb.SCHED_MERGE | hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(7, 0, 16) == hb.HB_ERR_INVALID_ARG
+    before7 = hb.get_schedule(7, hb.PREC_FP64)
+    hb.set_schedule(7, hb.PREC_FP64, hb.SCHED_MERGE)
+    assert hb.get_schedule(7, hb.PREC_FP64) == 8
+    hb.set_schedule(7, hb.PREC_FP64, before7)
     assert L.hb_set_schedule(7, 0, -1) == hb.HB_ERR_INVALID_ARG
     before = hb.get_schedule(7, hb.PREC_FP32_RR)
     hb.set_schedule(7, hb.PREC_FP32_RR, hb.SCHED_COLS_LDS)
     assert hb.get_schedule(7, hb.PREC_FP32_IR) == 1  # both mixed precisions name the FP32 operator
-    assert hb.get_schedule(7, hb.PREC_FP64) == 3
+    assert hb.get_schedule(7, hb.PREC_FP64) == 9
     hb.set_schedule(7, hb.PREC_FP32_RR, before)
     assert L.hb_autotune(0, 0, 0, 5, None, None) == hb.HB_ERR_INVALID_ARG
     assert L.hb_autotune(3, 0, 0, 10001, None, None) == hb.HB_ERR_INVALID_ARG

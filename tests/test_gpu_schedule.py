@@ -43,6 +43,8 @@ def relerr(a, b):
 
 
 def legal(N):
+    if N == 7:
+        return [0, 1, 2, 3, 8, 9]
     return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5]
 
 
@@ -82,6 +84,71 @@ def test_every_schedule_matches_oracle(nx, ny, nz, N):
         assert e64 <= 1e-12, (N, v)
         assert 1e-9 < e32 <= 2e-5, (N, v)
     m.close()
+
+
+# merged assembly (N = 7): four-element tiles along x; where 4 does not divide nx
+# each row ends in a short tile (padded rows), down to one element (nx = 1, 5)
+MERGE_BOXES = [(4, 1, 1, False), (8, 2, 1, False), (4, 3, 2, True), (8, 1, 2, True), (5, 2, 1, False),
+               (6, 2, 2, True), (7, 1, 3, False), (1, 2, 2, False), (3, 3, 1, True)]
+
+
+@pytest.mark.parametrize("nx,ny,nz,dirichlet", MERGE_BOXES)
+def test_merged_assembly_matches_oracle(nx, ny, nz, dirichlet):
+    N = 7
+    say(f"[case] merged assembly N=7 box {nx}x{ny}x{nz} dirichlet={dirichlet}")
+    m = hb.Mesh(nx, ny, nz, N, jitter=0.05, seed=40 + nx, fp32=True, dirichlet=dirichlet)
+    ref = oracle.Mesh(nx, ny, nz, N, jitter=0.05, seed=40 + nx, dirichlet=dirichlet)
+    x = inputs.random_vector(m.NG, 70 + nx)
+    yref = ref.ax(x, 0.9)
+    xd = torch.as_tensor(x, device=DEV)
+    for v in (hb.SCHED_MERGE, hb.SCHED_MERGE | hb.SCHED_COLS_LDS):
+        hb.set_schedule(N, hb.PREC_FP64, v)
+        hb.set_schedule(N, hb.PREC_FP32_RR, v)
+        y = torch.full((m.NG,), float("nan"), dtype=torch.float64, device=DEV)
+        m.ax(0.9, xd, y)
+        y32 = torch.full((m.NG,), float("nan"), dtype=torch.float32, device=DEV)
+        m.ax_f32(0.9, xd, y32)
+        e64, e32 = relerr(host(y), yref), relerr(host(y32), yref)
+        say(f"  schedule {v}: FP64 {e64:.2e} FP32 {e32:.2e}")
+        assert e64 <= 1e-12, v
+        assert 1e-9 < e32 <= 2e-5, v
+    m.close()
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_merged_cg_and_batch_match_default(dirichlet):
+    """The fused p.Ap partials and the batched kernel under the merged schedule:
+    60 fixed CG iterations agree with the default schedule to rounding."""
+    N = 7
+    say(f"[case] merged assembly CG + batch N=7 dirichlet={dirichlet}")
+    boxes = [(8, 2, 2, 1), (4, 3, 1, 2), (3, 2, 2, 3), (6, 2, 1, 4)]  # the last two: short tiles
+
+    def run():
+        ms, bs, xs = [], [], []
+        for nx, ny, nz, seed in boxes:
+            m = hb.Mesh(nx, ny, nz, N, jitter=0.05, seed=seed, dirichlet=dirichlet)
+            b = torch.empty(m.NG, dtype=torch.float64, device=DEV)
+            hb.rhs_uniform(b, 50 + seed)
+            ms.append(m)
+            bs.append(b)
+            xs.append(torch.empty_like(b))
+        single = torch.empty_like(bs[0])
+        r = ms[0].cg(0.5, bs[0], single, max_iter=60, fixed_iters=True)
+        assert r.status == hb.HB_OK and r.iters == 60
+        st, res = hb.batch_solve(ms, [0.5] * len(ms), bs, xs, max_iter=60, fixed_iters=True)
+        assert st == hb.HB_OK and all(q.iters == 60 for q in res)
+        out = [host(single)] + [host(x) for x in xs]
+        for m in ms:
+            m.close()
+        return out
+
+    hb.set_schedule(N, hb.PREC_FP64, 3)
+    x0 = run()
+    for v in (hb.SCHED_MERGE, hb.SCHED_MERGE | hb.SCHED_COLS_LDS):
+        hb.set_schedule(N, hb.PREC_FP64, v)
+        x1 = run()
+        for k, (a, b) in enumerate(zip(x0, x1)):
+            assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(a), (v, k)
 
 
 @pytest.mark.parametrize("v", [1, 2, 3])

@@ -1,8 +1,9 @@
 """The operator's tile order on a box mesh (walk.h): host-side checks of the very
 header the kernels include, compiled with the host compiler.  Every walk must be
 a permutation of the tiles (each tile visited once, none out of range), the
-identity where tiles would straddle rows, and it must bring z-neighbours within
-one slab plane (the locality it exists for)."""
+identity where tiles would straddle rows (padded rows: every element in exactly
+one tile, every tile in one row), and it must bring z-neighbours within one slab
+plane (the locality it exists for)."""
 import os
 import shutil
 import subprocess
@@ -36,8 +37,34 @@ static int check(int nx, int ny, int nz, int epb) {
     }
     return 0;
 }
+// padded rows: ceil(nx/epb) tiles per row; the spans of the walk's tiles cover
+// every element exactly once, each inside one row, the short one last in its row
+static int check_padded(int nx, int ny, int nz, int epb) {
+    const TileWalk w = make_walk(nx, ny, nz, epb, true);
+    const long E = (long)nx * ny * nz;
+    const long tpr = (nx + epb - 1) / epb, T = tpr * ny * nz;
+    if (walk_tiles(w, E, epb) != T || (long)w.txn != tpr) return 11;
+    if ((nx % epb == 0) != (w.rowlen == 0)) return 12;
+    std::vector<int> seen(E, 0), tseen(T, 0);
+    for (long j = 0; j < T; ++j) {
+        const uint32_t t = walk_tile(w, (uint32_t)j);
+        if ((long)t >= T || tseen[t]++) return 13;
+        const TileSpan sp = tile_span(w, t, E, epb);
+        if (sp.n < 1 || sp.n > epb || sp.e0 < 0 || sp.e0 + sp.n > E) return 14;
+        if (sp.e0 / nx != (sp.e0 + sp.n - 1) / nx) return 15;          // one row
+        if (sp.n < epb && (sp.e0 + sp.n) % nx != 0) return 16;          // short tiles end their row
+        for (int k = 0; k < sp.n; ++k) if (seen[sp.e0 + k]++) return 17;
+    }
+    for (long e = 0; e < E; ++e) if (seen[e] != 1) return 18;
+    return 0;
+}
 int main() {
     int bad = 0, n = 0;
+    for (int nx = 1; nx <= 13; ++nx)
+        for (int ny = 1; ny <= 11; ++ny)
+            for (int nz = 1; nz <= 3; ++nz)
+                for (int epb = 1; epb <= 5; ++epb) { int r = check_padded(nx, ny, nz, epb); ++n; if (r) { ++bad; std::printf("bad padded %d %d %d %d: %d\n", nx, ny, nz, epb, r); } }
+    { int r = check_padded(50, 50, 50, 4); ++n; if (r) { ++bad; std::printf("bad padded 50^3: %d\n", r); } }
     for (int nx = 1; nx <= 13; ++nx)
         for (int ny = 1; ny <= 19; ++ny)
             for (int nz = 1; nz <= 5; ++nz)
