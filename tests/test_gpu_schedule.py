@@ -101,6 +101,7 @@ def test_merged_assembly_matches_oracle(nx, ny, nz, dirichlet):
     x = inputs.random_vector(m.NG, 70 + nx)
     yref = ref.ax(x, 0.9)
     xd = torch.as_tensor(x, device=DEV)
+    y0 = inputs.random_vector(m.NG, 80 + nx)
     for v in (hb.SCHED_MERGE, hb.SCHED_MERGE | hb.SCHED_COLS_LDS):
         hb.set_schedule(N, hb.PREC_FP64, v)
         hb.set_schedule(N, hb.PREC_FP32_RR, v)
@@ -108,10 +109,15 @@ def test_merged_assembly_matches_oracle(nx, ny, nz, dirichlet):
         m.ax(0.9, xd, y)
         y32 = torch.full((m.NG,), float("nan"), dtype=torch.float32, device=DEV)
         m.ax_f32(0.9, xd, y32)
+        # the accumulating form adds to what y holds
+        ya = torch.as_tensor(y0, device=DEV).clone()
+        m.ax_add(0.9, xd, ya)
         e64, e32 = relerr(host(y), yref), relerr(host(y32), yref)
-        say(f"  schedule {v}: FP64 {e64:.2e} FP32 {e32:.2e}")
+        ea = relerr(host(ya), y0 + yref)
+        say(f"  schedule {v}: FP64 {e64:.2e} FP32 {e32:.2e} add {ea:.2e}")
         assert e64 <= 1e-12, v
         assert 1e-9 < e32 <= 2e-5, v
+        assert ea <= 1e-12, v
     m.close()
 
 
