@@ -56,8 +56,9 @@ __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkI
         double rz = 0.0;
         auto sweep = [&](auto Ap) {
             for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-                const double ri = r[i] - alpha * static_cast<double>(Ap[i]);
-                r[i] = ri;
+                const double ri = __builtin_nontemporal_load(&r[i]) -
+                                  alpha * static_cast<double>(__builtin_nontemporal_load(&Ap[i]));
+                __builtin_nontemporal_store(ri, &r[i]);
                 rr += ri * ri;
                 rz += ri * (inv[i] * ri);
             }
@@ -77,15 +78,16 @@ __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkI
     if (uniform(P.use32)) {
         const auto Ap = to_global(uniform(P.Ap32));
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const double ri = r[i] - alpha * static_cast<double>(Ap[i]);
-            r[i] = ri;
+            const double ri = __builtin_nontemporal_load(&r[i]) -
+                              alpha * static_cast<double>(__builtin_nontemporal_load(&Ap[i]));
+            __builtin_nontemporal_store(ri, &r[i]);
             rr += ri * ri;
         }
     } else {
         const auto Ap = to_global(uniform(P.Ap));
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const double ri = r[i] - alpha * Ap[i];
-            r[i] = ri;
+            const double ri = __builtin_nontemporal_load(&r[i]) - alpha * __builtin_nontemporal_load(&Ap[i]);
+            __builtin_nontemporal_store(ri, &r[i]);
             rr += ri * ri;
         }
     }
@@ -94,6 +96,8 @@ __global__ __launch_bounds__(kVecThreads) void batch_residual_kernel(const WorkI
 }
 
 // x += alpha p; p = r + beta p (Jacobi: p = inv r + beta p); Ap = 0 on one chunk.
+// x, r and Ap are accessed non-temporally here and in the residual step (as in
+// the single-problem kernels); p keeps plain stores for the operator's gather.
 __global__ __launch_bounds__(kVecThreads) void batch_update_kernel(const WorkItem *__restrict__ items,
                                                                   const BatchProb *__restrict__ probs)
 {
@@ -113,22 +117,22 @@ __global__ __launch_bounds__(kVecThreads) void batch_update_kernel(const WorkIte
         const auto inv = to_global(uniform(P.inv));
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
             const double pi = p[i];
-            x[i] += alpha * pi;
-            p[i] = inv[i] * r[i] + beta * pi;
+            __builtin_nontemporal_store(__builtin_nontemporal_load(&x[i]) + alpha * pi, &x[i]);
+            p[i] = inv[i] * __builtin_nontemporal_load(&r[i]) + beta * pi;
         }
     } else {
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
             const double pi = p[i];
-            x[i] += alpha * pi;
-            p[i] = r[i] + beta * pi;
+            __builtin_nontemporal_store(__builtin_nontemporal_load(&x[i]) + alpha * pi, &x[i]);
+            p[i] = __builtin_nontemporal_load(&r[i]) + beta * pi;
         }
     }
     if (uniform(P.use32)) {
         const auto Ap = to_global(uniform(P.Ap32));
-        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) Ap[i] = 0.0f;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) __builtin_nontemporal_store(0.0f, &Ap[i]);
     } else {
         const auto Ap = to_global(uniform(P.Ap));
-        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) Ap[i] = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) __builtin_nontemporal_store(0.0, &Ap[i]);
     }
 }
 
