@@ -266,8 +266,10 @@ def two_phase_vs_fused(hb, torch, metrics, B, n, N, dirichlet, label):
 def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
     """The 64 uneven problems: one-by-one FP64 CG vs the batched solver (FP64, FP64
     with the Jacobi preconditioner, and FP32 operator with FP64 residual
-    replacement without and with Jacobi, and with 25-iteration segments replayed
-    from captured graphs), all to rtol; solves/s."""
+    replacement without and with Jacobi, with 25-iteration segments replayed
+    from captured graphs, and with tile schedules tuned at the classes' sizes --
+    the first such run includes the timing, the second installs the cached
+    winners), all to rtol; solves/s."""
     cases = inputs.batched_cases()
     meshes, bs = [], []
     for c in cases:
@@ -287,17 +289,21 @@ def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
             iters += r.iters
         return iters
 
-    def batch(prec, graph_k=0, precond=hb.PRECOND_NONE):
+    def batch(prec, graph_k=0, precond=hb.PRECOND_NONE, autotune=False):
         st, res = hb.batch_solve(meshes, [c.lam for c in cases], bs, xs, max_iter=100000, rtol=rtol, prec=prec,
-                                 graph_k=graph_k, precond=precond)
+                                 graph_k=graph_k, precond=precond, autotune=autotune)
         assert st == hb.HB_OK, [r.status for r in res]
         return sum(r.iters for r in res)
 
+    # the autotuned runs change the FP32 table; restored afterwards
+    table = {N: hb.get_schedule(N, hb.PREC_FP32_RR) for N in sorted({c.N for c in cases})}
     for name, fn in (("sequential_fp64", seq), ("batched_fp64", lambda: batch(hb.PREC_FP64)),
                      ("batched_fp64_jacobi", lambda: batch(hb.PREC_FP64, precond=hb.PRECOND_JACOBI)),
                      ("batched_fp32rr", lambda: batch(hb.PREC_FP32_RR)),
                      ("batched_fp32rr_jacobi", lambda: batch(hb.PREC_FP32_RR, precond=hb.PRECOND_JACOBI)),
-                     ("batched_fp32rr_graphs", lambda: batch(hb.PREC_FP32_RR, graph_k=25))):
+                     ("batched_fp32rr_graphs", lambda: batch(hb.PREC_FP32_RR, graph_k=25)),
+                     ("batched_fp32rr_autotuned", lambda: batch(hb.PREC_FP32_RR, autotune=True)),
+                     ("batched_fp32rr_autotuned_again", lambda: batch(hb.PREC_FP32_RR, autotune=True))):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         iters = fn()
@@ -305,6 +311,11 @@ def batched_vs_sequential(hb, torch, inputs, rtol=1e-8):
         dt = time.perf_counter() - t0
         out[name] = {"solves_per_s": round(len(cases) / dt, 3), "wall_s": round(dt, 3), "cg_iterations": iters}
         print(f"# batch {name}: {len(cases) / dt:.2f} solves/s", file=sys.stderr, flush=True)
+    degrees = sorted({c.N for c in cases})
+    out["autotuned_schedules_fp32"] = {N: hb.get_schedule(N, hb.PREC_FP32_RR) for N in degrees}
+    for N, v in table.items():
+        hb.set_schedule(N, hb.PREC_FP32_RR, v)
+    out["default_schedules_fp32"] = table
     for m in meshes:
         m.close()
     return out
@@ -325,6 +336,13 @@ def served_vs_sequential(hb, torch, inputs, count, rtol=1e-8):
     for name, prec in (("engine_fp64_jacobi", hb.PREC_FP64), ("engine_fp32rr_jacobi", hb.PREC_FP32_RR)):
         out[name] = serving.replay_engine(trace, prec=prec, rtol=rtol, precond=hb.PRECOND_JACOBI, progress=16)
         print(f"# serving {name}: {out[name]}", file=sys.stderr, flush=True)
+    table = {N: hb.get_schedule(N, hb.PREC_FP32_RR) for N in range(1, 16)}
+    out["engine_fp32rr_jacobi_autotuned"] = serving.replay_engine(trace, prec=hb.PREC_FP32_RR, rtol=rtol,
+                                                                  precond=hb.PRECOND_JACOBI, progress=16,
+                                                                  autotune=True)
+    for N, v in table.items():
+        hb.set_schedule(N, hb.PREC_FP32_RR, v)
+    print(f"# serving autotuned: {out['engine_fp32rr_jacobi_autotuned']}", file=sys.stderr, flush=True)
     out["sequential_fp64"] = serving.replay_sequential(trace, rtol=rtol, progress=16)
     print(f"# serving sequential: {out['sequential_fp64']}", file=sys.stderr, flush=True)
     return out

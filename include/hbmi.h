@@ -200,6 +200,12 @@ typedef struct {
                             boxes (others use the per-step launches); same results up to the order of the
                             floating-point sums.  A barrier wait that times out ends the launch and the solve
                             with HB_ERR_DEVICE.  Ignored by hb_cg_solve.  0: per-step launches */
+    int32_t autotune;    /* hb_batch_solve: 1 first sets the tile schedule of each (degree, operator precision)
+                            class in the batch by timing every legal schedule on a synthetic box of the class's
+                            total local nodes (rounded down to a power of two in [2^16, 2^26]; each such size
+                            class is timed once per process, later calls install the cached winner).  Changes
+                            the process-wide schedule table (hb_get_schedule).  Ignored by hb_cg_solve.
+                            0: the table as it stands */
 } hb_cg_opts;
 
 typedef struct {
@@ -311,6 +317,9 @@ typedef struct {
     int32_t precond;        /* hb_precond: HB_PRECOND_JACOBI solves every request with the Jacobi
                                preconditioner (either precision), its 1 / diag(A) (8 N_G bytes) part of the
                                footprint */
+    int32_t autotune;       /* 1: at each admission, set the tile schedule of the request's (degree, operator
+                               precision) class for the class's running local nodes, as hb_cg_opts.autotune
+                               (each size class timed once per process); 0: the table as it stands */
 } hb_engine_opts;
 
 typedef struct {

@@ -65,7 +65,8 @@ class _MeshInfo(ctypes.Structure):
 class _EngineOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("iters_per_step", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("max_quota", ctypes.c_int32), ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("max_quota", ctypes.c_int32), ("graphs", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class _EngineInfo(ctypes.Structure):
@@ -77,7 +78,7 @@ class _CgOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
                 ("x0_zero", ctypes.c_int32), ("check_every", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_outer", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("graph_k", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("persistent", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class _CgResult(ctypes.Structure):
@@ -317,11 +318,12 @@ class Mesh:
 
 def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool = False, rtol: float = 1e-8,
                 x0_zero: bool = True, check_every: int = 0, prec: int = PREC_FP64, inner_rtol: float = 0.0,
-                graph_k: int = 0, precond: int = PRECOND_NONE, persistent: bool = False, stream=None,
-                raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
+                graph_k: int = 0, precond: int = PRECOND_NONE, persistent: bool = False, autotune: bool = False,
+                stream=None, raise_on=(HB_ERR_INVALID_ARG, HB_ERR_OUT_OF_MEMORY, HB_ERR_DEVICE)):
     """Solve independent problems together (hb_batch_solve); returns (status, [CgResult]).
     graph_k > 0: segments of graph_k iterations replayed from captured graphs; persistent: each segment
-    as one persistent launch holding every running problem (where their degrees and boxes allow)."""
+    as one persistent launch holding every running problem (where their degrees and boxes allow);
+    autotune: tile schedules of the batch's classes timed at the classes' sizes first."""
     import torch
 
     n = len(meshes)
@@ -336,7 +338,7 @@ def batch_solve(meshes, lams, bs, xs, *, max_iter: int = 100, fixed_iters: bool 
     X = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64) for x in xs])
     R = (_CgResult * n)()
     opts = _CgOpts(max_iter, int(fixed_iters), rtol, int(x0_zero), check_every, prec, 0, inner_rtol, graph_k,
-                   precond, int(persistent))
+                   precond, int(persistent), int(autotune))
     st = lib().hb_batch_solve(n, H, L, B, X, ctypes.byref(opts), R, _stream(stream))
     if st in raise_on:
         _check(st, "hb_batch_solve")
@@ -358,9 +360,9 @@ class Engine:
 
     def __init__(self, hbm_budget: int, max_slots: int, prec: int = PREC_FP32_RR, max_iter: int = 100000,
                  iters_per_step: int = 25, inner_rtol: float = 0.0, max_quota: int = 0, graphs: bool = False,
-                 precond: int = PRECOND_NONE, stream=None):
+                 precond: int = PRECOND_NONE, autotune: bool = False, stream=None):
         o = _EngineOpts(hbm_budget, max_slots, prec, max_iter, iters_per_step, inner_rtol, max_quota, int(graphs),
-                        precond)
+                        precond, int(autotune))
         h = ctypes.c_void_p()
         self._stream = _stream(stream)
         _check(lib().hb_engine_create(ctypes.byref(o), self._stream, ctypes.byref(h)), "hb_engine_create")

@@ -207,6 +207,13 @@ int ax_blocks_max(const hb_mesh_s *m);
 int ax_grid_for(int N, int64_t E, int64_t nx, int64_t ny, int64_t nz, int sched);
 // The order of the operator's tiles on an nx x ny x nz box under a schedule.
 TileWalk ax_walk_for(int N, int64_t nx, int64_t ny, int64_t nz, int sched);
+// The autotuner (tune.hip): time every legal schedule of a class on a synthetic
+// box of about local_nodes local nodes and install the fastest; the cached
+// form tunes each (degree, precision, power-of-two size class) once per
+// process and installs its winner on later calls.
+hb_status tune_class(int N, bool fp32, int64_t local_nodes, int reps, hb_tune_result *out, hipStream_t s);
+int tune_size_class(int64_t local_nodes);
+hb_status tune_class_cached(int N, bool fp32, int64_t local_nodes, hipStream_t s, int *schedule);
 // Schedule table (per degree and precision), shared by every solve path.
 int ax_schedule(int N, bool fp32);
 bool ax_schedule_legal(int N, int sched);

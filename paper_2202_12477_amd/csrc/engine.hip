@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -717,8 +718,15 @@ hb_status hb_batch_solve(int32_t nprob, const hb_mesh *meshes, const double *lam
     }
     if (nprob == 0) return HB_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    BatchRunner runner(nprob, s);
     hb_status st;
+    if (opts->autotune) {
+        // each (degree, operator precision) class at its total local nodes
+        std::map<int, int64_t> nodes;
+        for (int i = 0; i < nprob; ++i) nodes[meshes[i]->N] += meshes[i]->NL;
+        for (const auto &kv : nodes)
+            if ((st = tune_class_cached(kv.first, mixed, kv.second, s, nullptr))) return st;
+    }
+    BatchRunner runner(nprob, s);
     if ((st = runner.init())) return st;
     for (int i = 0; i < nprob; ++i)
         if ((st = runner.add(i, meshes[i], lambdas[i], dev_b[i], dev_x[i], *opts))) return st;
@@ -827,6 +835,16 @@ hb_status hb_engine_step(hb_engine e, int32_t iters, hb_engine_info *info)
         if ((st = hb_mesh_create(&r.desc, e->s, &a.mesh))) {
             e->release(a);
             return st;
+        }
+        if (e->opts.autotune) {
+            // the class's running local nodes with this request
+            int64_t nodes = a.mesh->NL;
+            for (const hb_engine_s::Active &o : e->active)
+                if (o.mesh && o.mesh->N == a.mesh->N) nodes += o.mesh->NL;
+            if ((st = tune_class_cached(a.mesh->N, e->opts.prec == HB_PREC_FP32_RR, nodes, e->s, nullptr))) {
+                e->release(a);
+                return st;
+            }
         }
         const int64_t NG = a.mesh->NG;
         size_t tally = 0;

@@ -8,6 +8,9 @@
 // caller inspect or pin entries.
 #include <cmath>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -71,8 +74,17 @@ hb_status hb_autotune(int32_t N, int32_t prec, int64_t local_nodes, int32_t reps
         return fail(HB_ERR_INVALID_ARG, "hb_autotune: local_nodes must be <= 2^30");
     if (reps <= 0) reps = 20;
     if (local_nodes <= 0) local_nodes = int64_t(1) << 22;
-    const bool fp32 = prec != HB_PREC_FP64;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return tune_class(N, prec != HB_PREC_FP64, local_nodes, reps, out, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace hb {
+
+hb_status tune_class(int N, bool fp32, int64_t local_nodes, int reps, hb_tune_result *out, hipStream_t s)
+{
+    hb_status st;
+    void *stream = s;
     const int n = std::max(1, static_cast<int>(std::lround(std::cbrt(static_cast<double>(local_nodes) /
                                                                      std::pow(N + 1.0, 3)))));
     hb_mesh_desc d{};
@@ -122,7 +134,7 @@ hb_status hb_autotune(int32_t N, int32_t prec, int64_t local_nodes, int32_t reps
         if (!e && he == hipSuccess) he = hipEventElapsedTime(&ms, t.e0, t.e1);
         if (e || he != hipSuccess) {
             set_ax_schedule(N, fp32, prev);
-            return e ? e : hip_fail(he, "hb_autotune: timing");
+            return e ? e : hip_fail(he, "autotune: timing");
         }
         res.us[v] = 1e3 * ms / reps;
         ++res.candidates;
@@ -136,4 +148,45 @@ hb_status hb_autotune(int32_t N, int32_t prec, int64_t local_nodes, int32_t reps
     return HB_OK;
 }
 
-}  // extern "C"
+namespace {
+
+// Winners per (degree, precision, size class), for the life of the process.
+struct TuneCache {
+    std::mutex m;
+    std::map<std::tuple<int, bool, int>, int> winner;
+};
+TuneCache &tune_cache()
+{
+    static TuneCache c;
+    return c;
+}
+
+}  // namespace
+
+int tune_size_class(int64_t local_nodes)
+{
+    // powers of two, clamped to [2^16, 2^26] local nodes
+    int k = 16;
+    while (k < 26 && (int64_t(1) << (k + 1)) <= local_nodes) ++k;
+    return k;
+}
+
+hb_status tune_class_cached(int N, bool fp32, int64_t local_nodes, hipStream_t s, int *schedule)
+{
+    const int k = tune_size_class(local_nodes);
+    const auto key = std::make_tuple(N, fp32, k);
+    TuneCache &c = tune_cache();
+    std::lock_guard<std::mutex> lock(c.m);
+    auto it = c.winner.find(key);
+    if (it == c.winner.end()) {
+        hb_tune_result r{};
+        hb_status st = tune_class(N, fp32, int64_t(1) << k, 20, &r, s);
+        if (st) return st;
+        it = c.winner.emplace(key, r.schedule).first;
+    }
+    if (ax_schedule(N, fp32) != it->second) set_ax_schedule(N, fp32, it->second);
+    if (schedule) *schedule = it->second;
+    return HB_OK;
+}
+
+}  // namespace hb

@@ -40,7 +40,7 @@ def _budget_extra(trace, budget, wall, done):
 
 
 def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, iters_per_step=25,
-                  max_iter=200000, precond=0, progress=None, budget=None):
+                  max_iter=200000, precond=0, progress=None, budget=None, autotune=False):
     """Submit each request when its arrival time has passed, step the engine while
     anything is queued or running, and poll for completions after every step.
     With `budget` (seconds) the loop stops at that wall time: the summary covers the
@@ -48,7 +48,7 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
     import torch
 
     eng = Engine(hbm_budget, max_slots=max_slots, prec=prec, max_iter=max_iter, iters_per_step=iters_per_step,
-                 precond=precond)
+                 precond=precond, autotune=autotune)
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()

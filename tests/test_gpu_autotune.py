@@ -1,0 +1,138 @@
+"""Tile schedules tuned at the workload's size (hb_cg_opts.autotune,
+hb_engine_opts.autotune).
+
+A batch solve with autotune first sets each (degree, operator precision)
+class's schedule from timings at the class's total size, so it may run other
+schedules than the default table: its fixed-iteration results agree with the
+default table's to rounding, every installed schedule is legal, and a second
+call installs the same winners (each size class is timed once per process).
+The engine does the same per admission; its results meet the tolerance.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2202_12477_amd as hb  # noqa: E402
+
+DEV = torch.device("cuda:0")
+PRECS = (hb.PREC_FP64, hb.PREC_FP32_RR)
+CASES = [inputs.BoxCase("t3", 4, 3, 2, 3, 0.05, 1, 31), inputs.BoxCase("t5", 2, 2, 3, 5, 0.05, 2, 32),
+         inputs.BoxCase("t7", 4, 2, 2, 7, 0.05, 3, 33), inputs.BoxCase("t7b", 3, 1, 2, 7, 0.05, 4, 34),
+         inputs.BoxCase("t9", 2, 1, 2, 9, 0.05, 5, 35)]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def legal(N):
+    if N == 7:
+        return {0, 1, 2, 3, 8, 9}
+    return {0, 1, 2, 3} if (N + 1) ** 2 <= 64 else {0, 1, 4, 5}
+
+
+@pytest.fixture(autouse=True)
+def restore_table():
+    saved = {(N, p): hb.get_schedule(N, p) for N in range(1, 16) for p in PRECS}
+    yield
+    for (N, p), v in saved.items():
+        hb.set_schedule(N, p, v)
+
+
+def run_batch(prec, autotune, fixed):
+    ms, bs, xs = [], [], []
+    for c in CASES:
+        m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=True)
+        b = torch.empty(m.NG, dtype=torch.float64, device=DEV)
+        hb.rhs_uniform(b, c.rhs_seed)
+        ms.append(m)
+        bs.append(b)
+        xs.append(torch.empty_like(b))
+    if fixed:
+        st, res = hb.batch_solve(ms, [c.lam for c in CASES], bs, xs, max_iter=60, fixed_iters=True,
+                                 autotune=autotune)
+    else:
+        st, res = hb.batch_solve(ms, [c.lam for c in CASES], bs, xs, max_iter=100000, rtol=1e-8, prec=prec,
+                                 autotune=autotune)
+    assert st == hb.HB_OK, [r.status for r in res]
+    torch.cuda.synchronize()
+    out = [x.cpu().numpy() for x in xs]
+    for m in ms:
+        m.close()
+    return out, res
+
+
+def test_batch_autotune_fp64_matches_default_table():
+    say("[case] batch FP64 60 fixed iterations, autotuned vs default table")
+    x0, r0 = run_batch(hb.PREC_FP64, False, True)
+    x1, r1 = run_batch(hb.PREC_FP64, True, True)
+    tuned = {N: hb.get_schedule(N, hb.PREC_FP64) for N in {c.N for c in CASES}}
+    say(f"  installed: {tuned}")
+    for N, v in tuned.items():
+        assert v in legal(N), (N, v)
+    for c, a, b, ra, rb in zip(CASES, x0, x1, r0, r1):
+        assert ra.iters == rb.iters == 60, c.name
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(a), c.name
+    # the same size classes again: the cached winners, not a new timing
+    for N in tuned:
+        hb.set_schedule(N, hb.PREC_FP64, 0)
+    run_batch(hb.PREC_FP64, True, True)
+    assert {N: hb.get_schedule(N, hb.PREC_FP64) for N in tuned} == tuned
+
+
+def test_batch_autotune_fp32rr_meets_tolerance():
+    say("[case] batch FP32 residual replacement to 1e-8, autotuned")
+    xs, res = run_batch(hb.PREC_FP32_RR, True, False)
+    for N in {c.N for c in CASES}:
+        assert hb.get_schedule(N, hb.PREC_FP32_RR) in legal(N)
+    for c, x, r in zip(CASES, xs, res):
+        ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+        bh = oracle.rhs(ref.NG, c.rhs_seed)
+        tr = np.linalg.norm(bh - ref.ax(x, c.lam)) / np.linalg.norm(bh)
+        say(f"  {c.name}: iters {r.iters} true residual {tr:.2e}")
+        assert r.status == hb.HB_OK and tr <= 1.2e-8, c.name
+
+
+def test_engine_autotune_meets_tolerance():
+    say("[case] engine FP32 residual replacement with autotune")
+    eng = hb.Engine(8 << 30, max_slots=3, prec=hb.PREC_FP32_RR, max_iter=100000, iters_per_step=20, autotune=True)
+    try:
+        tickets = {}
+        results = {}
+        pending = list(CASES)
+        for _ in range(100000):
+            if len(results) == len(CASES):
+                break
+            if pending:
+                c = pending.pop(0)
+                tickets[eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, lam=c.lam,
+                                   rhs_seed=c.rhs_seed, rtol=1e-8)] = c
+            eng.step()
+            for t in tickets:
+                if t not in results:
+                    out = eng.poll(t)
+                    if out is not None:
+                        results[t] = out
+        assert len(results) == len(CASES)
+    finally:
+        eng.close()
+    for N in {c.N for c in CASES}:
+        assert hb.get_schedule(N, hb.PREC_FP32_RR) in legal(N)
+    for t, c in tickets.items():
+        r, x = results[t]
+        ref = oracle.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+        bh = oracle.rhs(ref.NG, c.rhs_seed)
+        tr = np.linalg.norm(bh - ref.ax(x, c.lam)) / np.linalg.norm(bh)
+        say(f"  {c.name}: iters {r.iters} true residual {tr:.2e}")
+        assert r.status == hb.HB_OK and tr <= 1.2e-8, c.name
