@@ -36,8 +36,8 @@ namespace {
 // schedule by more than ~1.5%.
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 1, 3, 1, 3, 0, 0, 9, 0, 0, 0, 1, 4, 5, 5, 5},  // FP64
-    {0, 0, 3, 0, 0, 1, 0, 8, 0, 1, 1, 0, 0, 0, 1, 0},  // FP32
+    {0, 1, 1, 1, 3, 1, 0, 9, 0, 0, 0, 5, 5, 5, 5, 5},  // FP64
+    {0, 0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 0, 0, 0, 5, 4},  // FP32
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};

@@ -138,9 +138,9 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(16, 0, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
-    # measured defaults (autotuner at 2^24 local nodes), D^T from LDS for FP64 N = 11..14
-    fp64 = [1, 3, 1, 3, 0, 0, 9, 0, 0, 0, 1, 4, 5, 5, 5]
-    fp32 = [0, 3, 0, 0, 1, 0, 8, 0, 1, 1, 0, 0, 0, 1, 0]
+    # measured defaults (autotuner at 2^24 local nodes)
+    fp64 = [1, 1, 1, 3, 1, 0, 9, 0, 0, 0, 5, 5, 5, 5, 5]
+    fp32 = [0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 0, 0, 0, 5, 4]
     for N in range(1, 16):
         assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
         assert hb.get_schedule(N, hb.PREC_FP32_RR) == fp32[N - 1]
