@@ -328,6 +328,10 @@ typedef struct {
     int32_t completed;      /* finished, not yet polled */
     int32_t reserved;
     size_t used_bytes;      /* footprint of the admitted requests */
+    double admit_s;         /* host wall seconds spent admitting requests (mesh, forcing, CG start), since
+                               creation: the device runs nothing of the engine's meanwhile */
+    double iterate_s;       /* host wall seconds inside the steps' iterations (launches and their completion) */
+    double retire_s;        /* host wall seconds retiring requests (solution to host memory, release) */
 } hb_engine_info;
 
 /* Device bytes a request holds while admitted (pure host arithmetic), without a

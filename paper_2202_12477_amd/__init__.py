@@ -71,7 +71,8 @@ class _EngineOpts(ctypes.Structure):
 
 class _EngineInfo(ctypes.Structure):
     _fields_ = [("running", ctypes.c_int32), ("queued", ctypes.c_int32), ("completed", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("used_bytes", ctypes.c_size_t)]
+                ("reserved", ctypes.c_int32), ("used_bytes", ctypes.c_size_t), ("admit_s", ctypes.c_double),
+                ("iterate_s", ctypes.c_double), ("retire_s", ctypes.c_double)]
 
 
 class _CgOpts(ctypes.Structure):
@@ -393,7 +394,8 @@ class Engine:
     def step(self, iters: int = 0) -> dict:
         info = _EngineInfo()
         _check(lib().hb_engine_step(self._h, iters, ctypes.byref(info)), "hb_engine_step")
-        return dict(running=info.running, queued=info.queued, completed=info.completed, used_bytes=info.used_bytes)
+        return dict(running=info.running, queued=info.queued, completed=info.completed, used_bytes=info.used_bytes,
+                    admit_s=info.admit_s, iterate_s=info.iterate_s, retire_s=info.retire_s)
 
     def poll(self, ticket: int, want_x: bool = True):
         """None while running, else (CgResult, x as numpy array or None)."""

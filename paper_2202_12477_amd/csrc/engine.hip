@@ -14,6 +14,7 @@
 // its mesh and forcing on the device; a finished request's solution is copied
 // to host memory and its device memory is released for the next admission.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -669,6 +670,7 @@ struct hb_engine_s {
     std::unordered_map<uint64_t, Done> done;
     size_t used = 0;
     uint64_t next_ticket = 1;
+    double admit_s = 0.0, iterate_s = 0.0, retire_s = 0.0;  // host wall time per phase of the steps
 
     void release(Active &a)
     {
@@ -823,6 +825,9 @@ hb_status hb_engine_step(hb_engine e, int32_t iters, hb_engine_info *info)
 {
     if (!e) return fail(HB_ERR_INVALID_ARG, "hb_engine_step: null engine");
     hb_status st;
+    using clock = std::chrono::steady_clock;
+    auto since = [](clock::time_point t0) { return std::chrono::duration<double>(clock::now() - t0).count(); };
+    auto t0 = clock::now();
     // admission: first in, first out, while a slot is free and the footprint fits
     while (!e->queue.empty()) {
         const hb_engine_s::Request &r = e->queue.front();
@@ -868,8 +873,12 @@ hb_status hb_engine_step(hb_engine e, int32_t iters, hb_engine_info *info)
         e->active[slot] = a;
         e->queue.pop_front();
     }
+    e->admit_s += since(t0);
+    t0 = clock::now();
     const int k = iters > 0 ? iters : (e->opts.iters_per_step > 0 ? e->opts.iters_per_step : 25);
     if ((st = e->runner->step(k, e->opts.max_quota > 0 ? e->opts.max_quota : 64))) return st;
+    e->iterate_s += since(t0);
+    t0 = clock::now();
     // retire finished requests: solution to host memory, device memory released
     for (int i = 0; i < e->opts.max_slots; ++i) {
         hb_engine_s::Active &a = e->active[i];
@@ -883,12 +892,16 @@ hb_status hb_engine_step(hb_engine e, int32_t iters, hb_engine_info *info)
         e->runner->release(i);
         e->release(a);
     }
+    e->retire_s += since(t0);
     if (info) {
         info->running = e->runner->running();
         info->queued = static_cast<int32_t>(e->queue.size());
         info->completed = static_cast<int32_t>(e->done.size());
         info->reserved = 0;
         info->used_bytes = e->used;
+        info->admit_s = e->admit_s;
+        info->iterate_s = e->iterate_s;
+        info->retire_s = e->retire_s;
     }
     return HB_OK;
 }

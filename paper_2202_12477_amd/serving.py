@@ -53,6 +53,7 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nxt, lat, iters, steps, waiting = 0, [], 0, 0, {}
+        info = {}
         while len(lat) < len(trace):
             now = time.perf_counter() - t0
             if budget is not None and now >= budget:
@@ -69,7 +70,8 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
                     pause = min(pause, budget - (time.perf_counter() - t0))
                 time.sleep(max(0.0, pause))
                 continue
-            ready = eng.step()["completed"]  # results waiting to be polled
+            info = eng.step()
+            ready = info["completed"]  # results waiting to be polled
             steps += 1
             for t in list(waiting):
                 if ready == 0:
@@ -89,7 +91,9 @@ def replay_engine(trace, *, prec, rtol=1e-8, hbm_budget=64 << 30, max_slots=32, 
         wall = time.perf_counter() - t0
     finally:
         eng.close()
-    extra = {"engine_steps": steps}
+    # host wall time the engine spent per phase of its steps (admission and
+    # retirement leave the device without engine work)
+    extra = {"engine_steps": steps, **{k: round(info.get(k, 0.0), 3) for k in ("admit_s", "iterate_s", "retire_s")}}
     if budget is not None:
         extra.update(_budget_extra(trace, budget, wall, len(lat)))
     return _summary(lat, wall, iters, extra)
