@@ -369,10 +369,6 @@ class BatchRunner {
             *out = gexec_;
             return HB_OK;
         }
-        if (gexec_) {
-            (void)hipGraphExecDestroy(gexec_);
-            gexec_ = nullptr;
-        }
         if (!cap_s_) HB_HIP(hipStreamCreateWithFlags(&cap_s_, hipStreamNonBlocking));
         HB_HIP(hipStreamBeginCapture(cap_s_, hipStreamCaptureModeThreadLocal));
         const hb_status st = enqueue_step(iters, cap_s_);
@@ -381,6 +377,24 @@ class BatchRunner {
         if (st != HB_OK || e != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             return st != HB_OK ? st : hip_fail(e, "hipStreamEndCapture");
+        }
+        if (gexec_) {
+            // the same launches with other lists and grids (a problem retired or
+            // joined, the class set unchanged): update the executable graph in
+            // place instead of instantiating a new one
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult why{};
+            if (hipGraphExecUpdate(gexec_, graph, &bad, &why) == hipSuccess && why == hipGraphExecUpdateSuccess) {
+                (void)hipGraphDestroy(graph);
+                ++g_updates_;
+                g_iters_ = iters;
+                g_version_ = lists_version_;
+                *out = gexec_;
+                return HB_OK;
+            }
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(gexec_);
+            gexec_ = nullptr;
         }
         const hipError_t ei = hipGraphInstantiate(&gexec_, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -618,6 +632,7 @@ class BatchRunner {
     hipStream_t cap_s_ = nullptr;
     hipGraphExec_t gexec_ = nullptr;
     int g_iters_ = 0;
+    int g_updates_ = 0;  // executable graphs updated in place (instead of instantiated anew)
     uint64_t lists_version_ = 0, g_version_ = 0;
 };
 
