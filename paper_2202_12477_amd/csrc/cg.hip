@@ -154,15 +154,18 @@ __global__ __launch_bounds__(kFinThreads) void beta_kernel(const double *__restr
 
 // x += alpha p; p = r + beta p (PC: p = inv r + beta p); Ap = 0 (the next
 // operator call assembles into it).
-template <typename TAp, bool PC>
+template <typename TAp, bool PC, bool AP_CACHED>
 __global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *__restrict__ x, double *__restrict__ p,
                                                             const double *__restrict__ r, TAp *__restrict__ Ap,
                                                             const double *__restrict__ inv, const CgState *st)
 {
     if (st->done) return;
     const double alpha = st->alpha, beta = st->beta;
-    // x, r and Ap non-temporal (not read again before the next update or
-    // residual step); p with plain stores, which the operator gathers next
+    // x and r non-temporal (not read again before the next update or residual
+    // step); p with plain stores, which the operator gathers next.  Ap with
+    // plain stores where it fits the last-level cache with room to spare
+    // (AP_CACHED), so the operator's memory-side atomic adds find its lines
+    // there; non-temporal otherwise.
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const double pi = p[i];
         __builtin_nontemporal_store(__builtin_nontemporal_load(&x[i]) + alpha * pi, &x[i]);
@@ -171,7 +174,10 @@ __global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *
             p[i] = inv[i] * ri + beta * pi;
         else
             p[i] = ri + beta * pi;
-        __builtin_nontemporal_store(TAp(0), &Ap[i]);
+        if constexpr (AP_CACHED)
+            Ap[i] = TAp(0);
+        else
+            __builtin_nontemporal_store(TAp(0), &Ap[i]);
     }
 }
 
@@ -369,10 +375,22 @@ template <typename TAp>
 hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp *Ap, const double *inv, CgState *st,
                            hipStream_t s)
 {
-    if (inv)
-        update_kernel<TAp, true><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, inv, st);
-    else
-        update_kernel<TAp, false><<<vec_blocks(n), kVecThreads, 0, s>>>(n, x, p, r, Ap, nullptr, st);
+    // Ap of at most 128 MB (half the last-level cache) is cleared with plain
+    // stores: at 32^3 N=7 (91 MB) a CG iteration took 336 us against 345 us with
+    // non-temporal stores, on the 50^3 Dirichlet box (340 MB) 1493 us against 1481 us
+    const bool cached = static_cast<uint64_t>(n) * sizeof(TAp) <= (uint64_t(128) << 20);
+    const int g = vec_blocks(n);
+    if (inv) {
+        if (cached)
+            update_kernel<TAp, true, true><<<g, kVecThreads, 0, s>>>(n, x, p, r, Ap, inv, st);
+        else
+            update_kernel<TAp, true, false><<<g, kVecThreads, 0, s>>>(n, x, p, r, Ap, inv, st);
+    } else {
+        if (cached)
+            update_kernel<TAp, false, true><<<g, kVecThreads, 0, s>>>(n, x, p, r, Ap, nullptr, st);
+        else
+            update_kernel<TAp, false, false><<<g, kVecThreads, 0, s>>>(n, x, p, r, Ap, nullptr, st);
+    }
     HB_HIP(hipGetLastError());
     return HB_OK;
 }
