@@ -16,18 +16,17 @@ constexpr int kFinThreads = 1024;
 __device__ inline double sum_partials(const double *partial, int n, double *scratch)
 {
     // eight loads in flight per thread, added in index order (the same sums as a
-    // plain strided loop, without waiting on each load)
+    // plain strided loop, without waiting on each load; past the end a thread
+    // adds zeros, which leaves its sum unchanged)
     double s = 0.0;
     const int step = blockDim.x;
-    int i = threadIdx.x;
-    for (; i + 7 * step < n; i += 8 * step) {
+    for (int i = threadIdx.x; i < n; i += 8 * step) {
         double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = partial[i + k * step];
+        for (int k = 0; k < 8; ++k) v[k] = i + k * step < n ? partial[i + k * step] : 0.0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) s += v[k];
     }
-    for (; i < n; i += step) s += partial[i];
     return block_sum(s, scratch);
 }
 
