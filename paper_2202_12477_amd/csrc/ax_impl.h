@@ -133,11 +133,12 @@ __device__ inline void atomic_add(gptr<T> p, T v)
 // an out-of-line call would spill the whole register set.)
 // rows: the tile's elements are x-consecutive in one row of the box (the
 // merged assembly needs it; without it that schedule assembles node by node).
+// map_nt (CG form): stream the map non-temporally.
 template <int N, bool DOT, typename T, int V, bool MASK, bool LOCAL = false>
 __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gptr<const int32_t> __restrict__ map,
                                gptr<const T> __restrict__ geo, gptr<const T> __restrict__ Dm, T lambda,
                                gptr<const double> __restrict__ x, gptr<T> __restrict__ y,
-                               gptr<double> __restrict__ dot_out, bool rows = false)
+                               gptr<double> __restrict__ dot_out, bool rows = false, bool map_nt = true)
 {
     using S = AxShape<N, V>;
     constexpr int n1 = S::n1, np2 = S::np2, np3 = S::np3, epb = S::epb;
@@ -200,10 +201,10 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
     gptr<const uint32_t> me = (gptr<const uint32_t>)map + eo * np3 + ab;
 #pragma unroll
     for (int c = 0; c < n1; ++c) {
-        // inside CG (DOT) the vector kernels evict everything between operator
-        // calls, and a non-temporal map stream keeps p and Ap in the caches;
-        // back to back, the map itself is reused from the last-level cache
-        if constexpr (DOT)
+        // back to back, the map itself is reused from the last-level cache;
+        // inside CG (DOT) too where map, p and Ap fit that cache together, else
+        // a non-temporal map stream keeps p and Ap there
+        if (DOT && map_nt)
             idx[c] = __builtin_nontemporal_load(&me[c * np2]);
         else
             idx[c] = me[c * np2];
@@ -442,7 +443,7 @@ __global__ __launch_bounds__((AxShape<N, V>::threads))
 __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
     int64_t E, TileWalk walk, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm,
     T lambda, const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial,
-    const CgState *__restrict__ st)
+    const CgState *__restrict__ st, int map_nt)
 {
     if constexpr (DOT) {
         // stopped, or stopping at the next alpha step (which reads no partials)
@@ -452,7 +453,8 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
     // x-consecutive elements of one row
     const TileSpan sp = tile_span(walk, walk_tile(walk, xcd_remap(blockIdx.x, gridDim.x)), E, AxShape<N, V>::epb);
     ax_tile<N, DOT, T, V, MASK>(sp, to_global(map), to_global(geo), to_global(Dm), lambda, to_global(x),
-                                to_global(y), to_global(DOT ? partial + blockIdx.x : partial), walk.txn != 0);
+                                to_global(y), to_global(DOT ? partial + blockIdx.x : partial), walk.txn != 0,
+                                map_nt != 0);
 }
 
 // First phase of the two-phase operator: y_L = (S_L + lambda C) Z x per element
@@ -589,12 +591,18 @@ hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambd
         const int grid = static_cast<int>(walk_tiles(walk, m->E, AxShape<N, V>::epb));
         if (grid == 0) return HB_OK;
         const T lam = static_cast<T>(lambda);
+        // CG: map (4 N_L bytes), p (8 N_G) and Ap (sizeof(T) N_G) within the
+        // 256 MB last-level cache: plain map loads (32^3 N=7, 249 MB: 333 against
+        // 338 us per iteration); above it non-temporal (50^3 Dirichlet: 1488
+        // against 1504 us)
+        const bool map_nt = static_cast<uint64_t>(m->NL) * 4 + static_cast<uint64_t>(m->NG) * (8 + sizeof(T)) >
+                            (uint64_t(256) << 20);
         if (st)
             ax_kernel<N, true, T, V, MASK><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
-                                                                             y, partial, st);
+                                                                             y, partial, st, map_nt ? 1 : 0);
         else
             ax_kernel<N, false, T, V, MASK><<<grid, AxShape<N, V>::threads, 0, s>>>(m->E, walk, m->map, geo, D, lam, x,
-                                                                              y, nullptr, nullptr);
+                                                                              y, nullptr, nullptr, 0);
         HB_HIP(hipGetLastError());
         return HB_OK;
     });
