@@ -135,6 +135,39 @@ def test_engine_follows_a_schedule_change_between_steps():
         assert tr <= 1.2 * TOL
 
 
+def test_engine_reports_host_time_per_phase():
+    """hb_engine_info's cumulative host times: admission, iterations and
+    retirement are each counted, grow monotonically, and add up to no more than
+    the wall time of the steps."""
+    import time
+
+    say("[case] engine phase times")
+    eng = hb.Engine(4 << 30, max_slots=2, prec=hb.PREC_FP64, max_iter=100000, iters_per_step=10)
+    try:
+        tickets = [eng.submit(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, rhs_seed=c.rhs_seed, rtol=TOL)
+                   for c in REQS[:3]]
+        last = dict(admit_s=0.0, iterate_s=0.0, retire_s=0.0)
+        wall, done = 0.0, set()
+        for _ in range(100000):
+            if len(done) == len(tickets):
+                break
+            t0 = time.perf_counter()
+            info = eng.step()
+            wall += time.perf_counter() - t0
+            for k in last:
+                assert info[k] >= last[k]
+                last[k] = info[k]
+            for t in tickets:
+                if t not in done and eng.poll(t, want_x=False) is not None:
+                    done.add(t)
+        assert len(done) == len(tickets)
+    finally:
+        eng.close()
+    say(f"  {last}, steps' wall {wall:.3f} s")
+    assert last["admit_s"] > 0 and last["iterate_s"] > 0 and last["retire_s"] > 0
+    assert sum(last.values()) <= wall + 1e-3
+
+
 def test_engine_rejects_requests_larger_than_budget():
     eng = hb.Engine(10 << 20, max_slots=2, prec=hb.PREC_FP64)
     with pytest.raises(hb.HbError) as e:
