@@ -10,7 +10,7 @@ by its known bytes, give the factor that turns the counters into HBM bytes for
 the operator's launches.
 
   python -m paper_2202_12477_amd.profile_ax [--case box32_N7_affine | sweepN] [--launches K] [--fp32 | --gather]
-      [--pcg K]
+      [--pcg K] [--cg K]
   python -m paper_2202_12477_amd.profile_ax --cases sweep9 sweep12 sweep2:fp32 ... [--launches K]
 
 --cases runs several operators one after the other in one process (a case with
@@ -19,7 +19,8 @@ pass covers them all; each case's launches are announced on stdout first.
 
 --pcg K then also runs K fixed iterations of Jacobi-preconditioned FP64 CG on
 the same mesh (its vector kernels: residual_kernel<double, true>,
-update_kernel<double, true>).
+update_kernel<double, true, ...>); --cg K the same with plain CG
+(residual_kernel<double, false>, update_kernel<double, false, ...>).
 """
 from __future__ import annotations
 
@@ -39,6 +40,7 @@ def main():
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--gather", action="store_true")
     ap.add_argument("--pcg", type=int, default=0)
+    ap.add_argument("--cg", type=int, default=0)
     ap.add_argument("--cases", nargs="*", default=None, help="several cases (suffix :fp32 for the FP32 operator)")
     args = ap.parse_args()
     if args.cases:
@@ -73,13 +75,18 @@ def main():
         y = torch.zeros_like(b)
         for _ in range(args.launches):
             m.ax_add(c.lam, b, y)
+    if args.cg > 0:
+        x = torch.empty_like(b)
+        r = m.cg(c.lam, b, x, max_iter=args.cg, fixed_iters=True, history=False)
+        assert r.iters == args.cg and r.status == hb.HB_OK, r
+        del x
     if args.pcg > 0:
         x = torch.empty_like(b)
         r = m.cg(c.lam, b, x, max_iter=args.pcg, fixed_iters=True, history=False, precond=hb.PRECOND_JACOBI)
         assert r.iters == args.pcg and r.status == hb.HB_OK, r
         del x
     torch.cuda.synchronize()
-    print(f"operator {c.name}{' dirichlet' if args.dirichlet else ''} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={args.launches} pcg={args.pcg} "
+    print(f"operator {c.name}{' dirichlet' if args.dirichlet else ''} E={m.E} N={c.N} NG={m.NG} NL={m.NL} launches={args.launches} pcg={args.pcg} cg={args.cg} "
           f"{'fp32' if args.fp32 else 'fp64'}{' two-phase' if args.gather else ''}", flush=True)
     m.close()
     del b, y
