@@ -185,6 +185,39 @@ def paper_workload(hb, torch, metrics, B, n=50, N=7):
     return out
 
 
+def small_config(hb, torch, inputs, reps=5):
+    """The small configuration (4^3 jittered hexahedra, N=3, 2197 DOFs): one operator
+    application and 100 fixed CG iterations, timed as launched one kernel at a time
+    and as replays of one captured 100-iteration graph (best of reps, after a warm-up);
+    at this size every step is launch- and latency-bound."""
+    c = inputs.PLAIN_SMALL
+    m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed)
+    b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
+    hb.rhs_uniform(b, c.rhs_seed)
+    x = torch.empty_like(b)
+    y = torch.empty_like(b)
+    out = {"workload": f"{c.nx}x{c.ny}x{c.nz} jittered box, N={c.N}, {m.NG} DOFs, lambda={c.lam}"}
+
+    def best(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            fn()
+            e.record()
+            e.synchronize()
+            ts.append(s.elapsed_time(e) * 1e-3)
+        return min(ts)
+
+    out["ax_us"] = round(best(lambda: m.ax(c.lam, b, y)) * 1e6, 2)
+    for name, gk in (("cg_us_per_iter", 0), ("cg_graph_us_per_iter", c.iters)):
+        t = best(lambda: m.cg(c.lam, b, x, max_iter=c.iters, fixed_iters=True, history=False, graph_k=gk))
+        out[name] = round(t / c.iters * 1e6, 2)
+    m.close()
+    return out
+
+
 def jacobi_vs_plain(hb, torch, n=32, N=7, jitter=0.2, rtol=1e-8):
     """Jacobi-preconditioned CG beside plain CG on a deformed Dirichlet box
     (n^3 elements with jittered vertices, N=7, FP64, U[-1,1) forcing): the cost
@@ -475,6 +508,7 @@ def main():
     }
     m.close()
     del b, y, yk, x
+    out["small_config"] = small_config(hb, torch, inputs)
     out["paper_workload"] = paper_workload(hb, torch, metrics, B)
     if not args.no_jacobi:
         out["jacobi"] = jacobi_vs_plain(hb, torch)
