@@ -181,6 +181,75 @@ __global__ __launch_bounds__(kVecThreads) void update_kernel(int64_t n, double *
     }
 }
 
+// The four steps after the operator -- alpha, r -= alpha Ap with r.r, beta,
+// x += alpha p; p = r + beta p (PC: p = inv r + beta p); Ap = 0 -- in one
+// workgroup, for vectors so short that one workgroup streams them in less time
+// than four dependent launches take.  The same steps and state transitions as
+// alpha_kernel, residual_kernel, beta_kernel and update_kernel; r.r is summed
+// over the one workgroup (one partial), so only the grouping of its additions
+// differs.
+template <typename TAp, bool PC>
+__global__ __launch_bounds__(kFinThreads) void tail_kernel(int64_t n, double *__restrict__ x, double *__restrict__ p,
+                                                          double *__restrict__ r, TAp *__restrict__ Ap,
+                                                          const double *__restrict__ inv,
+                                                          const double *__restrict__ part_ax, int nax,
+                                                          double *__restrict__ part_vec, CgState *st,
+                                                          double *__restrict__ rho, double *__restrict__ hist)
+{
+    // each thread holds its K entries (i = threadIdx.x + k blockDim.x) in
+    // registers from the residual to the update, every load of a pass in flight
+    constexpr int K = static_cast<int>(kCgTailMax / kFinThreads);
+    __shared__ double red[kFinThreads / 64];
+    alpha_step(part_ax, nax, st, rho);
+    __syncthreads();  // thread 0's state update, seen by the whole workgroup
+    if (st->done) return;
+    const double alpha = st->alpha;
+    const int t = threadIdx.x, step = blockDim.x;
+    double rv[K], zv[PC ? K : 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t i = t + static_cast<int64_t>(k) * step;
+        rv[k] = i < n ? r[i] - alpha * static_cast<double>(Ap[i]) : 0.0;
+        if constexpr (PC) zv[k] = i < n ? inv[i] : 0.0;
+    }
+    double rr = 0.0, rz = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t i = t + static_cast<int64_t>(k) * step;
+        if (i < n) r[i] = rv[k];
+        rr += rv[k] * rv[k];
+        if constexpr (PC) rz += rv[k] * (zv[k] * rv[k]);
+    }
+    rr = block_sum(rr, red);
+    if constexpr (PC) rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        part_vec[0] = PC ? rz : rr;
+        if (PC) part_vec[1] = rr;
+    }
+    __syncthreads();
+    beta_step(part_vec, 1, st, rho, hist, PC);
+    __syncthreads();
+    const double beta = st->beta;
+    double pv[K], xv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t i = t + static_cast<int64_t>(k) * step;
+        pv[k] = i < n ? p[i] : 0.0;
+        xv[k] = i < n ? x[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t i = t + static_cast<int64_t>(k) * step;
+        if (i >= n) continue;
+        x[i] = xv[k] + alpha * pv[k];
+        if constexpr (PC)
+            p[i] = zv[k] * rv[k] + beta * pv[k];
+        else
+            p[i] = rv[k] + beta * pv[k];
+        Ap[i] = TAp(0);
+    }
+}
+
 // Diagonal of the assembled operator, one thread per local node: at node
 // (a,b,c) of an element, (D^T G D + lambda C)_ii = sum_m D[m][a]^2 G_rr(m,b,c)
 // + sum_m D[m][b]^2 G_ss(a,m,c) + sum_m D[m][c]^2 G_tt(a,b,m)
@@ -395,6 +464,20 @@ hb_status launch_cg_update(int64_t n, double *x, double *p, const double *r, TAp
     return HB_OK;
 }
 
+template <typename TAp>
+hb_status launch_cg_tail(int64_t n, double *x, double *p, double *r, TAp *Ap, const double *inv, CgWork &w, int nax,
+                         CgState *st, hipStream_t s)
+{
+    if (inv)
+        tail_kernel<TAp, true><<<1, kFinThreads, 0, s>>>(n, x, p, r, Ap, inv, w.part_ax, nax, w.part_vec, st, w.rho,
+                                                         w.hist);
+    else
+        tail_kernel<TAp, false><<<1, kFinThreads, 0, s>>>(n, x, p, r, Ap, nullptr, w.part_ax, nax, w.part_vec, st,
+                                                          w.rho, w.hist);
+    HB_HIP(hipGetLastError());
+    return HB_OK;
+}
+
 hb_status launch_jacobi_inverse(const hb_mesh_s *m, double lambda, double *inv, hipStream_t s)
 {
     if (m->NG == 0) return HB_OK;
@@ -410,6 +493,10 @@ template hb_status launch_cg_init<double>(int64_t, const double *, double *, dou
                                           CgWork &, CgState *, hipStream_t);
 template hb_status launch_cg_init<float>(int64_t, const double *, double *, double *, double *, float *, int,
                                          CgWork &, CgState *, hipStream_t);
+template hb_status launch_cg_tail<double>(int64_t, double *, double *, double *, double *, const double *, CgWork &,
+                                          int, CgState *, hipStream_t);
+template hb_status launch_cg_tail<float>(int64_t, double *, double *, double *, float *, const double *, CgWork &,
+                                         int, CgState *, hipStream_t);
 template hb_status launch_cg_residual<double>(int64_t, double *, const double *, CgWork &, CgState *, hipStream_t);
 template hb_status launch_cg_residual<float>(int64_t, double *, const float *, CgWork &, CgState *, hipStream_t);
 template hb_status launch_cg_update<double>(int64_t, double *, double *, const double *, double *, const double *,

@@ -107,6 +107,9 @@ hb_status enqueue_iteration(hb_mesh_s *m, CgWork &w, double lambda, double *x, T
     const int64_t n = m->NG;
     hb_status e;
     if ((e = apply_op(m, lambda, w.p, Ap, w.part_ax, w.state, s))) return e;
+    if (n <= kCgTailMax)  // short vectors: the four steps after the operator in one workgroup
+        return launch_cg_tail<TAp>(n, x, w.p, w.r, Ap, w.pc ? w.jinv : nullptr, w, ax_blocks(m, sizeof(TAp) == 4),
+                                   w.state, s);
     if ((e = launch_cg_alpha(w, ax_blocks(m, sizeof(TAp) == 4), w.state, s))) return e;
     if ((e = launch_cg_residual<TAp>(n, w.r, Ap, w, w.state, s))) return e;
     if ((e = launch_cg_beta(n, w, w.state, s))) return e;
