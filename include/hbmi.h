@@ -365,7 +365,10 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 /* 256-thread workgroup four x-consecutive elements, one per wave, sums      */
 /* their shared faces in LDS and assembles each row of 4N+1 DOFs once       */
 /* (where 4 does not divide nx, each row of the box ends in a shorter tile). */
-/* Schedule values are 0..15.  The choice changes the reduction grouping of  */
+/* Schedule values are 0..15.  While a class's entry is the built-in default */
+/* (neither set nor autotuned), a single-problem launch of fewer than 256    */
+/* workgroups (a tiny mesh) uses the one-wave form of that schedule where    */
+/* an element fits a wave.  The choice changes the reduction grouping of     */
 /* p.Ap, the order of assembly atomics and of the t-part sums only (results  */
 /* agree to rounding).  The table is process-wide, starts from measured      */
 /* defaults, and must not be changed while solves are in flight.  `prec`:    */

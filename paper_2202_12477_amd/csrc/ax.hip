@@ -41,6 +41,7 @@ constexpr int kDefaultSched[2][kMaxN + 1] = {
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};
+std::atomic<bool> g_explicit[2][kMaxN + 1] = {};  // set by a caller or the autotuner
 std::atomic<int> g_epoch{0};
 std::once_flag g_init;
 
@@ -73,6 +74,7 @@ void set_ax_schedule(int N, bool fp32, int v)
 {
     init_table();
     g_sched[fp32 ? 1 : 0][N].store(v, std::memory_order_relaxed);
+    g_explicit[fp32 ? 1 : 0][N].store(true, std::memory_order_relaxed);
     g_epoch.fetch_add(1);
 }
 
@@ -149,10 +151,23 @@ int ax_grid_for(int N, int64_t E, int64_t nx, int64_t ny, int64_t nz, int sched)
     return static_cast<int>(walk_tiles(ax_walk_for(N, nx, ny, nz, sched), E, ax_epb_for(N, sched)));
 }
 
+int mesh_schedule(const hb_mesh_s *m, bool fp32)
+{
+    const int v = ax_schedule(m->N, fp32);
+    if (g_explicit[fp32 ? 1 : 0][m->N].load(std::memory_order_relaxed)) return v;  // a chosen schedule, as is
+    const int wave = (v & kSchedColsLds) | kSchedWave;
+    // a launch of fewer workgroups than the device has CUs is latency-bound:
+    // one-wave workgroups (more of them) where an element fits a wave
+    if (!(v & kSchedWave) && ax_schedule_legal(m->N, wave) &&
+        ax_grid_for(m->N, m->E, m->desc.nx, m->desc.ny, m->desc.nz, v) < kSmallLaunch)
+        return wave;
+    return v;
+}
+
 int ax_blocks(const hb_mesh_s *m, bool fp32)
 {
     if (!fp32 && (m->desc.flags & HB_MESH_GATHER)) return ax_local_blocks(m);
-    return ax_grid_for(m->N, m->E, m->desc.nx, m->desc.ny, m->desc.nz, ax_schedule(m->N, fp32));
+    return ax_grid_for(m->N, m->E, m->desc.nx, m->desc.ny, m->desc.nz, mesh_schedule(m, fp32));
 }
 
 int ax_blocks_max(const hb_mesh_s *m)

@@ -585,7 +585,7 @@ template <int N, typename T, bool MASK>
 hb_status launch_ax_n(const hb_mesh_s *m, const T *geo, const T *D, double lambda, const double *x, T *y,
                       double *partial, CgState *st, hipStream_t s)
 {
-    return with_schedule<N>(ax_schedule(N, sizeof(T) == 4), [&](auto VV) -> hb_status {
+    return with_schedule<N>(mesh_schedule(m, sizeof(T) == 4), [&](auto VV) -> hb_status {
         constexpr int V = decltype(VV)::value;
         const TileWalk walk = ax_walk<N, V>(m->desc.nx, m->desc.ny, m->desc.nz);
         const int grid = static_cast<int>(walk_tiles(walk, m->E, AxShape<N, V>::epb));

@@ -214,6 +214,13 @@ TileWalk ax_walk_for(int N, int64_t nx, int64_t ny, int64_t nz, int sched);
 hb_status tune_class(int N, bool fp32, int64_t local_nodes, int reps, hb_tune_result *out, hipStream_t s);
 int tune_size_class(int64_t local_nodes);
 hb_status tune_class_cached(int N, bool fp32, int64_t local_nodes, hipStream_t s, int *schedule);
+// The schedule a single-problem launch on this mesh uses: the table's; while
+// the class's entry is the built-in default (no hb_set_schedule or autotuning
+// for it yet), launches of fewer than kSmallLaunch workgroups where an element
+// fits a wave take its one-wave form (the small configuration: 13.4 us per CG
+// iteration against 14.5 us).  ax_blocks counts the workgroups of this one.
+constexpr int kSmallLaunch = 256;
+int mesh_schedule(const hb_mesh_s *m, bool fp32);
 // Schedule table (per degree and precision), shared by every solve path.
 int ax_schedule(int N, bool fp32);
 bool ax_schedule_legal(int N, int sched);
