@@ -364,8 +364,12 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 /* waves per SIMD (N >= 8); bit 3 (8, N = 7 only, not with bit 1) gives a    */
 /* 256-thread workgroup four x-consecutive elements, one per wave, sums      */
 /* their shared faces in LDS and assembles each row of 4N+1 DOFs once       */
-/* (where 4 does not divide nx, each row of the box ends in a shorter tile). */
-/* Schedule values are 0..15.  While a class's entry is the built-in default */
+/* (where 4 does not divide nx, each row of the box ends in a shorter tile); */
+/* bit 4 (16, N >= 8, only with bits 0 and 2, i.e. value 21) also reads the  */
+/* rows of D from LDS, keeps the map column in LDS between gather and        */
+/* assembly, prefetches one geometry layer instead of two (FP64) and targets */
+/* three waves per SIMD.                                                     */
+/* Schedule values are 0..31.  While a class's entry is the built-in default */
 /* (neither set nor autotuned), a single-problem launch of fewer than 256    */
 /* workgroups (a tiny mesh) uses the one-wave form of that schedule where    */
 /* an element fits a wave.  The choice changes the reduction grouping of     */
@@ -378,7 +382,7 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 typedef struct {
     int32_t schedule;   /* the schedule chosen (now in the table) */
     int32_t candidates; /* schedules timed */
-    double us[16];      /* mean launch time per schedule value in microseconds; < 0: not available here */
+    double us[32];      /* mean launch time per schedule value in microseconds; < 0: not available here */
 } hb_tune_result;
 
 /* Current schedule of a class. */
@@ -389,7 +393,8 @@ hb_status hb_set_schedule(int32_t N, int32_t prec, int32_t schedule);
  * of about `local_nodes` local nodes (<= 0: 2^22; at most 2^30; the best
  * schedule depends on the problem size, so tune at the size that will run),
  * built and freed here (device allocation), `reps` back-to-back y += A x
- * launches each (<= 0: 20; at most 10000), and put the fastest in the table.
+ * launches each (<= 0: 20; at most 10000) after 128 untimed launches that
+ * bring the device up to speed, and put the fastest in the table.
  * out may be NULL.  Synchronises `stream`. */
 hb_status hb_autotune(int32_t N, int32_t prec, int64_t local_nodes, int32_t reps, hb_tune_result *out,
                       void *stream);

@@ -29,7 +29,7 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-st
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so with gcc."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.tmp"  # per process: parallel test workers build at once
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -45,7 +45,7 @@ TIMING_CFLAGS = ["-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math", 
 
 def build_timing() -> str:
     """Compile oracle.c into liboracle_omp.so (timing build) with gcc."""
-    tmp = _LIB_OMP + ".tmp"
+    tmp = f"{_LIB_OMP}.{os.getpid()}.tmp"
     subprocess.check_call(["gcc", *TIMING_CFLAGS, "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _LIB_OMP)
     return _LIB_OMP

@@ -88,8 +88,11 @@ class _CgResult(ctypes.Structure):
                 ("fp64_iters", ctypes.c_int32), ("persistent_segments", ctypes.c_int32)]
 
 
+NUM_SCHED = 32  # tile schedule values 0..31 (hb_tune_result.us)
+
+
 class _TuneResult(ctypes.Structure):
-    _fields_ = [("schedule", ctypes.c_int32), ("candidates", ctypes.c_int32), ("us", ctypes.c_double * 16)]
+    _fields_ = [("schedule", ctypes.c_int32), ("candidates", ctypes.c_int32), ("us", ctypes.c_double * NUM_SCHED)]
 
 
 _lib = None
@@ -424,6 +427,7 @@ SCHED_COLS_LDS = 1
 SCHED_WAVE = 2
 SCHED_LEAN = 4
 SCHED_MERGE = 8
+SCHED_THREE = 16
 
 
 def get_schedule(N: int, prec: int = PREC_FP64) -> int:
@@ -444,7 +448,7 @@ def autotune(N: int, prec: int = PREC_FP64, local_nodes: int = 0, reps: int = 20
     r = _TuneResult()
     _check(lib().hb_autotune(N, prec, local_nodes, reps, ctypes.byref(r), _stream(stream)), "hb_autotune")
     return {"N": N, "prec": prec, "schedule": r.schedule, "candidates": r.candidates,
-            "us": {v: round(r.us[v], 2) for v in range(16) if r.us[v] >= 0}}
+            "us": {v: round(r.us[v], 2) for v in range(NUM_SCHED) if r.us[v] >= 0}}
 
 
 def stream_probe(inp, out, stream=None):

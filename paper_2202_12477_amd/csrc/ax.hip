@@ -31,13 +31,13 @@ namespace {
 
 // Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups, N <= 7;
 // bit 2: lean registers with two waves per SIMD, N >= 8; bit 3: merged row
-// assembly, N = 7): the autotuner's choices on this part at about 2^24 local
-// nodes per degree (the order-sweep size), kept where the winner beat the plain
-// schedule by more than ~1.5%.
+// assembly, N = 7; bit 4: the three-wave form of 5, N >= 8): the autotuner's
+// choices on this part at about 2^24 local nodes per degree (the order-sweep
+// size), kept where the winner beat the plain schedule by more than ~1.5%.
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 1, 1, 1, 3, 1, 0, 9, 0, 0, 0, 5, 5, 5, 5, 5},  // FP64
-    {0, 0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 0, 0, 0, 5, 4},  // FP32
+    {0, 1, 1, 1, 3, 1, 0, 9, 0, 21, 0, 21, 21, 5, 5, 5},  // FP64
+    {0, 0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 21, 0, 21, 5, 4},  // FP32
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};
@@ -66,8 +66,10 @@ bool ax_schedule_legal(int N, int v)
 {
     const bool small = (N + 1) * (N + 1) <= 64;  // an element fits in a wave
     const bool wave = (N + 1) * (N + 1) == 64;   // an element is exactly a wave
+    const int lean_cols = kSchedLean | kSchedColsLds;
     return N >= 1 && N <= kMaxN && v >= 0 && v < kNumSched && (!(v & kSchedWave) || small) &&
-           (!(v & kSchedLean) || !small) && (!(v & kSchedMerge) || (wave && !(v & kSchedWave)));
+           (!(v & kSchedLean) || !small) && (!(v & kSchedMerge) || (wave && !(v & kSchedWave))) &&
+           (!(v & kSchedThree) || (v & lean_cols) == lean_cols);
 }
 
 void set_ax_schedule(int N, bool fp32, int v)

@@ -75,6 +75,14 @@ constexpr bool kLeanLegal = !kWaveLegal<N>;
 //                   rows of 8.
 template <int N>
 constexpr bool kMergeLegal = (N + 1) * (N + 1) == 64;
+//   kSchedThree   - (with kSchedLean and kSchedColsLds) D's rows and the map
+//                   column also live in LDS, FP64 prefetches one geometry layer
+//                   instead of two, and the target is three waves per SIMD: at
+//                   the degrees where that fits without spills (FP64 N = 9, 11,
+//                   12) the third wave hides more of the layer loop's latency
+//                   than the extra LDS reads cost.
+template <int V>
+constexpr int kWavesTarget = (V & kSchedLean) ? ((V & kSchedThree) ? 3 : 2) : 1;
 // the merged schedule's tiles lie in one row of the box, so its walk pads the rows
 template <int N, int V>
 constexpr bool kPadRows = (V & kSchedMerge) != 0 && kMergeLegal<N>;
@@ -167,11 +175,18 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
     // rows a, b of D in registers, loaded once; columns a, b likewise, or D^T in LDS
     constexpr bool cols_lds = (V & kSchedColsLds) != 0;
     __shared__ T sDt[cols_lds ? np2 : 1];
-    T Da[n1], Db[n1], DaT[cols_lds ? 1 : n1], DbT[cols_lds ? 1 : n1];
+    // three-wave form: rows of D in LDS as well, and the map column parked there
+    // between the gather and the assembly
+    constexpr bool three = (V & kSchedThree) != 0 && cols_lds && (V & kSchedLean) != 0;
+    __shared__ T sD[three ? np2 : 1];
+    __shared__ uint32_t sidx[three && !LOCAL ? epb * np3 : 1];
+    T Da[three ? 1 : n1], Db[three ? 1 : n1], DaT[cols_lds ? 1 : n1], DbT[cols_lds ? 1 : n1];
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
-        Da[m] = Dm[a * n1 + m];
-        Db[m] = Dm[b * n1 + m];
+        if constexpr (!three) {
+            Da[m] = Dm[a * n1 + m];
+            Db[m] = Dm[b * n1 + m];
+        }
         if constexpr (!cols_lds) {
             DaT[m] = Dm[m * n1 + a];
             DbT[m] = Dm[m * n1 + b];
@@ -192,6 +207,8 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
     if constexpr (cols_lds) {
         // sDt[i][m] = D[m][i]; the first layer's barriers order these stores before any read
         for (int i = t; i < np2; i += S::threads) sDt[(i % n1) * n1 + i / n1] = Dm[i];
+        if constexpr (three)
+            for (int i = t; i < np2; i += S::threads) sD[i] = Dm[i];
         if constexpr (merge) __syncthreads();  // filled by the first wave, read by all
     }
 
@@ -220,11 +237,18 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
 #pragma unroll
         for (int c = 0; c < n1; ++c) q[c] = static_cast<T>(x[idx[c]]);
     }
+    if constexpr (three && !LOCAL) {
+        // read back by the same thread before its atomics
+        if (lane_used) {
+#pragma unroll
+            for (int c = 0; c < n1; ++c) sidx[el * np3 + c * np2 + ab] = idx[c];
+        }
+    }
 
     // G is streamed once: non-temporal loads keep it from evicting x and y from
     // the caches (above a line per element and factor, geo_load).  Layers c+1 .. c+PF are in flight while layer c is computed
     // (a ring of PF register sets; the loop is unrolled, so slots are static).
-    constexpr int PF = kPrefetch < n1 ? kPrefetch : n1;
+    constexpr int PF = (three && sizeof(T) == 8) ? 1 : (kPrefetch < n1 ? kPrefetch : n1);
     // geometry layout [E][layer c][factor f][(N+1)^2 nodes of the layer]
     gptr<const T> ge = geo + eo * kGeo * np3 + ab;
     constexpr bool geo_nt = np2 * sizeof(T) >= 128;
@@ -271,8 +295,13 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
         T qr = 0, qs = 0;
 #pragma unroll
         for (int m = 0; m < n1; ++m) {
-            qr += Da[m] * sq[cb][el][b * n1 + m];
-            qs += Db[m] * sq[cb][el][m * n1 + a];
+            if constexpr (three) {
+                qr += sD[a * n1 + m] * sq[cb][el][b * n1 + m];
+                qs += sD[b * n1 + m] * sq[cb][el][m * n1 + a];
+            } else {
+                qr += Da[m] * sq[cb][el][b * n1 + m];
+                qs += Db[m] * sq[cb][el][m * n1 + a];
+            }
         }
         const T fr = G[0] * qr + G[1] * qs + G[2] * qt;
         const T fs = G[1] * qr + G[3] * qs + G[4] * qt;
@@ -413,6 +442,10 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
                 atomic_add(&y[idx[c]], recv ? yv[c] + v_next : yv[c]);
         }
     } else if (active) {
+        if constexpr (three) {
+#pragma unroll
+            for (int c = 0; c < n1; ++c) idx[c] = sidx[el * np3 + c * np2 + ab];
+        }
         if constexpr (MASK) {
 #pragma unroll
             for (int c = 0; c < n1; ++c)
@@ -440,7 +473,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
 
 template <int N, bool DOT, typename T, int V, bool MASK>
 __global__ __launch_bounds__((AxShape<N, V>::threads))
-__attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
+__attribute__((amdgpu_waves_per_eu(kWavesTarget<V>))) void ax_kernel(
     int64_t E, TileWalk walk, const int32_t *__restrict__ map, const T *__restrict__ geo, const T *__restrict__ Dm,
     T lambda, const double *__restrict__ x, T *__restrict__ y, double *__restrict__ partial,
     const CgState *__restrict__ st, int map_nt)
@@ -461,7 +494,7 @@ __attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_kernel(
 // (no assembly), with the same tiles and optional p.Ap partials as ax_kernel.
 template <int N, bool DOT, int V, bool MASK>
 __global__ __launch_bounds__((AxShape<N, V>::threads))
-__attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void ax_local_kernel(
+__attribute__((amdgpu_waves_per_eu(kWavesTarget<V>))) void ax_local_kernel(
     int64_t E, TileWalk walk, const int32_t *__restrict__ map, const double *__restrict__ geo,
     const double *__restrict__ Dm, double lambda, const double *__restrict__ x, double *__restrict__ yl,
     double *__restrict__ partial, const CgState *__restrict__ st)
@@ -502,7 +535,7 @@ __device__ inline double uniform(double v)
 // through scalar loads.
 template <int N, typename T, int V, bool MASK>
 __global__ __launch_bounds__((AxShape<N, V>::threads))
-__attribute__((amdgpu_waves_per_eu((V & kSchedLean) ? 2 : 1))) void batch_ax_kernel(const WorkItem *__restrict__ items,
+__attribute__((amdgpu_waves_per_eu(kWavesTarget<V>))) void batch_ax_kernel(const WorkItem *__restrict__ items,
                                                                          const BatchProb *__restrict__ probs,
                                                                          const T *__restrict__ Dm)
 {
@@ -552,7 +585,11 @@ constexpr int legal_sched(int v)
 {
     // merging needs the 256-thread tile: it drops the one-wave bit
     const int m = v & (kMergeLegal<N> ? kSchedMerge : 0);
-    return (v & (kSchedColsLds | (kWaveLegal<N> && !m ? kSchedWave : 0) | (kLeanLegal<N> ? kSchedLean : 0))) | m;
+    // the three-wave form needs the lean schedule with D^T in LDS
+    constexpr int both = kSchedColsLds | kSchedLean;
+    const int three = kLeanLegal<N> && (v & both) == both ? (v & kSchedThree) : 0;
+    return (v & (kSchedColsLds | (kWaveLegal<N> && !m ? kSchedWave : 0) | (kLeanLegal<N> ? kSchedLean : 0))) | m |
+           three;
 }
 template <int N, typename F>
 decltype(auto) with_schedule(int v, F &&f)
@@ -565,6 +602,7 @@ decltype(auto) with_schedule(int v, F &&f)
     case 5: return f(std::integral_constant<int, legal_sched<N>(5)>{});
     case 8: return f(std::integral_constant<int, legal_sched<N>(8)>{});
     case 9: return f(std::integral_constant<int, legal_sched<N>(9)>{});
+    case 21: return f(std::integral_constant<int, legal_sched<N>(21)>{});
     default: return f(std::integral_constant<int, 0>{});
     }
 }

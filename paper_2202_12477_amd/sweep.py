@@ -2,7 +2,8 @@
 
 For every degree N: the FP64 operator (hb_ax_add) and the FP32 operator
 (hb_ax_f32: output cleared, then the operator) timed with HIP events on the
-launching stream, as algorithmic GB/s and GDOF/s; the FP32 operator's relative
+launching stream (median of three runs after 128 untimed launches), as
+algorithmic GB/s and GDOF/s; the FP32 operator's relative
 difference from the FP64 one on the same input; and with --solve, FP64 CG vs
 the two mixed-precision solvers to a relative residual (solves timed end to
 end, true residual reported by each solver); with --two-phase, y = A x by the
@@ -38,15 +39,22 @@ def main():
     from paper_2202_12477_amd import metrics
 
     def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(reps):
+        # 128 untimed launches (after each mesh's host set-up the device has been
+        # idle, and its first ~100 launches run up to 15% slow at FP64 N = 9-12),
+        # then the median of three timed runs of `reps` launches
+        for _ in range(128):
             fn()
-        e.record()
-        e.synchronize()
-        return s.elapsed_time(e) * 1e-3 / reps
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            for _ in range(reps):
+                fn()
+            e.record()
+            e.synchronize()
+            runs.append(s.elapsed_time(e) * 1e-3 / reps)
+        return sorted(runs)[1]
 
     for N in args.degrees:
         c = inputs.order_sweep_case(N)

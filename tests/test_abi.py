@@ -139,8 +139,8 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
     # measured defaults (autotuner at 2^24 local nodes)
-    fp64 = [1, 1, 1, 3, 1, 0, 9, 0, 0, 0, 5, 5, 5, 5, 5]
-    fp32 = [0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 0, 0, 0, 5, 4]
+    fp64 = [1, 1, 1, 3, 1, 0, 9, 0, 21, 0, 21, 21, 5, 5, 5]
+    fp32 = [0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 21, 0, 21, 5, 4]
     for N in range(1, 16):
         assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
         assert hb.get_schedule(N, hb.PREC_FP32_RR) == fp32[N - 1]
@@ -155,7 +155,15 @@ def test_schedule_table_validation(L):
     assert L.hb_set_schedule(8, 0, hb.SCHED_MERGE) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(3, 0, hb.SCHED_MERGE) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(7, 0, hb.SCHED_MERGE | hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
+    # the three-wave form: N >= 8, with the lean schedule and D^T in LDS only
     assert L.hb_set_schedule(7, 0, 16) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(7, 0, 16 | 5) == hb.HB_ERR_INVALID_ARG
+    for v in (16, 16 | hb.SCHED_LEAN, 16 | hb.SCHED_COLS_LDS, 32):
+        assert L.hb_set_schedule(11, 0, v) == hb.HB_ERR_INVALID_ARG, v
+    before11 = hb.get_schedule(11, hb.PREC_FP32_RR)
+    hb.set_schedule(11, hb.PREC_FP32_RR, hb.SCHED_THREE | hb.SCHED_LEAN | hb.SCHED_COLS_LDS)
+    assert hb.get_schedule(11, hb.PREC_FP32_RR) == 21
+    hb.set_schedule(11, hb.PREC_FP32_RR, before11)
     before7 = hb.get_schedule(7, hb.PREC_FP64)
     hb.set_schedule(7, hb.PREC_FP64, hb.SCHED_MERGE)
     assert hb.get_schedule(7, hb.PREC_FP64) == 8

@@ -41,7 +41,7 @@ def relerr(a, b):
 
 
 def legal(N):
-    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5]
+    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5, 21]
 
 
 @pytest.fixture(autouse=True)

@@ -45,7 +45,7 @@ def relerr(a, b):
 def legal(N):
     if N == 7:
         return [0, 1, 2, 3, 8, 9]
-    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5]
+    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5, 21]
 
 
 @pytest.fixture(autouse=True)
@@ -173,6 +173,30 @@ def test_cg_history_under_schedule(v):
     assert res.status == hb.HB_OK and res.iters == c.iters
     href, bar = history_bar(ref, oracle.rhs(m.NG, c.rhs_seed), c.lam, c.iters)
     assert compare_history(res.history, href, bar) <= 1.0
+    m.close()
+
+
+@pytest.mark.parametrize("N", [9, 11, 12])
+def test_cg_history_three_wave_form(N):
+    """The CG form of the operator (fused p.Ap partials) under the three-wave
+    form and under the lean schedule it extends: both 60-iteration histories stay
+    inside the oracle envelope on a jittered box with a ragged tile count."""
+    nx, ny, nz, lam = 3, 1, 1, 0.9
+    say(f"[case] CG N={N} box {nx}x{ny}x{nz}, schedules 5 and 21")
+    m = hb.Mesh(nx, ny, nz, N, jitter=0.05, seed=70 + N)
+    ref = oracle.Mesh(nx, ny, nz, N, jitter=0.05, seed=70 + N)
+    b = torch.empty(m.NG, dtype=torch.float64, device=DEV)
+    hb.rhs_uniform(b, 80 + N)
+    href, bar = history_bar(ref, oracle.rhs(m.NG, 80 + N), lam, 60)
+    xs = []
+    for v in (hb.SCHED_LEAN | hb.SCHED_COLS_LDS, hb.SCHED_THREE | hb.SCHED_LEAN | hb.SCHED_COLS_LDS):
+        hb.set_schedule(N, hb.PREC_FP64, v)
+        x = torch.empty_like(b)
+        res = m.cg(lam, b, x, max_iter=60, fixed_iters=True)
+        assert res.status == hb.HB_OK and res.iters == 60
+        assert compare_history(res.history, href, bar) <= 1.0, v
+        xs.append(host(x))
+    assert np.linalg.norm(xs[0] - xs[1]) <= 1e-9 * np.linalg.norm(xs[0])
     m.close()
 
 
