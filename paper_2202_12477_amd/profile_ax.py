@@ -14,8 +14,10 @@ the operator's launches.
   python -m paper_2202_12477_amd.profile_ax --cases sweep9 sweep12 sweep2:fp32 ... [--launches K]
 
 --cases runs several operators one after the other in one process (a case with
-the suffix ":fp32" is the FP32 operator on that mesh), so that one profiler
-pass covers them all; each case's launches are announced on stdout first.
+the suffix ":fp32" is the FP32 operator on that mesh; "@V" after it runs tile
+schedule V instead of the class's default, e.g. sweep11@5 or sweep11:fp32@0), so
+that one profiler pass covers them all; each case's launches are announced on
+stdout first.
 
 --pcg K then also runs K fixed iterations of Jacobi-preconditioned FP64 CG on
 the same mesh (its vector kernels: residual_kernel<double, true>,
@@ -109,9 +111,14 @@ def run_cases(cases, launches):
 
     named = {k.name: k for k in (inputs.PLAIN_SMALL, inputs.PLAIN_LARGE)}
     for spec in cases:
+        spec, _, sched = spec.partition("@")
         name, _, kind = spec.partition(":")
         fp32 = kind == "fp32"
         c = inputs.order_sweep_case(int(name[5:])) if name.startswith("sweep") else named[name]
+        prec = hb.PREC_FP32_RR if fp32 else hb.PREC_FP64
+        saved = hb.get_schedule(c.N, prec)
+        if sched:
+            hb.set_schedule(c.N, prec, int(sched))
         m = hb.Mesh(c.nx, c.ny, c.nz, c.N, jitter=c.jitter, seed=c.mesh_seed, fp32=fp32)
         b = torch.empty(m.NG, dtype=torch.float64, device="cuda")
         hb.rhs_uniform(b, c.rhs_seed)
@@ -129,6 +136,8 @@ def run_cases(cases, launches):
         torch.cuda.synchronize()
         m.close()
         del b, y
+        if sched:
+            hb.set_schedule(c.N, prec, saved)
     inp = torch.ones(8 * STREAM_N, dtype=torch.float64, device="cuda")
     out = torch.empty(STREAM_N, dtype=torch.float64, device="cuda")
     for _ in range(launches):
