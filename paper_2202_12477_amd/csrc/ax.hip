@@ -13,12 +13,13 @@ namespace hb {
                             hipStream_t);                                                                       \
     hb_status launch_ax32_##n(const hb_mesh_s *, double, const double *, float *, double *, CgState *,          \
                               hipStream_t);                                                                     \
-    hb_status launch_batch_ax_##n(const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t);   \
+    hb_status launch_batch_ax_##n(int, const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t); \
     hb_status launch_ax_d_##n(const hb_mesh_s *, double, const double *, double *, double *, CgState *,         \
                               hipStream_t);                                                                     \
     hb_status launch_ax32_d_##n(const hb_mesh_s *, double, const double *, float *, double *, CgState *,        \
                                 hipStream_t);                                                                   \
-    hb_status launch_batch_ax_d_##n(const void *, bool, const WorkItem *, int, const BatchProb *, hipStream_t); \
+    hb_status launch_batch_ax_d_##n(int, const void *, bool, const WorkItem *, int, const BatchProb *,           \
+                                    hipStream_t);                                                             \
     int ax_epb_##n(int);                                                                                        \
     TileWalk ax_walk_##n(int64_t, int64_t, int64_t, int);
 HB_DECL_AX(1) HB_DECL_AX(2) HB_DECL_AX(3) HB_DECL_AX(4) HB_DECL_AX(5) HB_DECL_AX(6) HB_DECL_AX(7) HB_DECL_AX(8)
@@ -31,13 +32,13 @@ namespace {
 
 // Default schedules (bit 0: D^T in LDS; bit 1: one-wave workgroups, N <= 7;
 // bit 2: lean registers with two waves per SIMD, N >= 8; bit 3: merged row
-// assembly, N = 7; bit 4: the three-wave form of 5, N >= 8): the autotuner's
+// assembly, N <= 10; bit 4: the three-wave form of 5, N >= 8): the autotuner's
 // choices on this part at about 2^24 local nodes per degree (the order-sweep
 // size), kept where the winner beat the plain schedule by more than ~1.5%.
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 1, 1, 1, 3, 1, 0, 9, 0, 21, 0, 21, 21, 5, 5, 5},  // FP64
-    {0, 0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 21, 0, 21, 5, 4},  // FP32
+    {0, 1, 1, 9, 3, 1, 8, 9, 8, 21, 8, 21, 21, 5, 5, 5},  // FP64
+    {0, 8, 1, 8, 1, 9, 9, 8, 9, 9, 9, 21, 0, 21, 5, 4},   // FP32
 };
 
 std::atomic<int> g_sched[2][kMaxN + 1] = {};
@@ -64,11 +65,11 @@ int ax_schedule(int N, bool fp32)
 
 bool ax_schedule_legal(int N, int v)
 {
-    const bool small = (N + 1) * (N + 1) <= 64;  // an element fits in a wave
-    const bool wave = (N + 1) * (N + 1) == 64;   // an element is exactly a wave
+    const bool small = (N + 1) * (N + 1) <= 64;   // an element fits in a wave
+    const bool merge = (N + 1) * (N + 1) <= 128;  // a 256-thread tile holds two or more elements
     const int lean_cols = kSchedLean | kSchedColsLds;
     return N >= 1 && N <= kMaxN && v >= 0 && v < kNumSched && (!(v & kSchedWave) || small) &&
-           (!(v & kSchedLean) || !small) && (!(v & kSchedMerge) || (wave && !(v & kSchedWave))) &&
+           (!(v & kSchedLean) || !small) && (!(v & kSchedMerge) || (merge && !(v & (kSchedWave | kSchedLean | kSchedThree)))) &&
            (!(v & kSchedThree) || (v & lean_cols) == lean_cols);
 }
 
@@ -112,14 +113,14 @@ hb_status launch_ax32(const hb_mesh_s *m, double lambda, const double *x, float 
     }
 }
 
-hb_status launch_batch_ax(int N, const void *D, bool fp32, bool dirichlet, const WorkItem *items, int nitems,
-                          const BatchProb *probs, hipStream_t s)
+hb_status launch_batch_ax(int N, int sched, const void *D, bool fp32, bool dirichlet, const WorkItem *items,
+                          int nitems, const BatchProb *probs, hipStream_t s)
 {
     switch (N) {
-#define HB_CASE(n)                                                                \
-    case n:                                                                       \
-        return dirichlet ? launch_batch_ax_d_##n(D, fp32, items, nitems, probs, s) \
-                         : launch_batch_ax_##n(D, fp32, items, nitems, probs, s);
+#define HB_CASE(n)                                                                       \
+    case n:                                                                              \
+        return dirichlet ? launch_batch_ax_d_##n(sched, D, fp32, items, nitems, probs, s) \
+                         : launch_batch_ax_##n(sched, D, fp32, items, nitems, probs, s);
         HB_ALL_N(HB_CASE)
 #undef HB_CASE
     default: return fail(HB_ERR_INVALID_ARG, "unsupported degree N");
@@ -153,10 +154,19 @@ int ax_grid_for(int N, int64_t E, int64_t nx, int64_t ny, int64_t nz, int sched)
     return static_cast<int>(walk_tiles(ax_walk_for(N, nx, ny, nz, sched), E, ax_epb_for(N, sched)));
 }
 
+int unmerged_if_sparse(int N, bool fp32, int v, int64_t elements, int64_t tiles)
+{
+    if (!(v & kSchedMerge) || g_explicit[fp32 ? 1 : 0][N].load(std::memory_order_relaxed)) return v;
+    const double slots = static_cast<double>(tiles) * ax_epb_for(N, v);
+    return static_cast<double>(elements) < kMergeFill * slots ? (v & ~kSchedMerge) : v;
+}
+
 int mesh_schedule(const hb_mesh_s *m, bool fp32)
 {
-    const int v = ax_schedule(m->N, fp32);
+    int v = ax_schedule(m->N, fp32);
     if (g_explicit[fp32 ? 1 : 0][m->N].load(std::memory_order_relaxed)) return v;  // a chosen schedule, as is
+    if (v & kSchedMerge)
+        v = unmerged_if_sparse(m->N, fp32, v, m->E, ax_grid_for(m->N, m->E, m->desc.nx, m->desc.ny, m->desc.nz, v));
     const int wave = (v & kSchedColsLds) | kSchedWave;
     // a launch of fewer workgroups than the device has CUs is latency-bound:
     // one-wave workgroups (more of them) where an element fits a wave

@@ -64,17 +64,17 @@ template <int N>
 constexpr bool kWaveLegal = (N + 1) * (N + 1) <= 64;
 template <int N>
 constexpr bool kLeanLegal = !kWaveLegal<N>;
-//   kSchedMerge   - (N = 7, where an element is exactly one wave) a 256-thread
-//                   workgroup holds four x-consecutive elements, one per wave,
-//                   whose layer loops synchronise within their wave only; at
-//                   the end the workgroup sums the three faces the elements
+//   kSchedMerge   - (N <= 10, where a 256-thread workgroup holds two or more
+//                   elements) the workgroup's epb elements are x-consecutive in
+//                   one row of the box; at the end it sums the epb-1 faces they
 //                   share in LDS and assembles each of the tile's (N+1)^2 rows
-//                   of 4N+1 consecutive DOFs once.  Each atomic add is a
+//                   of epb N + 1 consecutive DOFs once.  Each atomic add is a
 //                   read-modify-write at the memory side on this part, and a
-//                   row of 29 DOFs goes out in fewer, fuller requests than four
-//                   rows of 8.
+//                   row of 29 DOFs (N = 7) goes out in fewer, fuller requests
+//                   than four rows of 8.  At N = 7 an element is exactly one
+//                   wave, and the layer loops synchronise within their wave.
 template <int N>
-constexpr bool kMergeLegal = (N + 1) * (N + 1) == 64;
+constexpr bool kMergeLegal = (N + 1) * (N + 1) <= 128;
 //   kSchedThree   - (with kSchedLean and kSchedColsLds) D's rows and the map
 //                   column also live in LDS, FP64 prefetches one geometry layer
 //                   instead of two, and the target is three waves per SIMD: at
@@ -195,8 +195,9 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
     // merged assembly: each wave holds one element and its own LDS slices, so the
     // layer loop synchronises within the wave (LDS writes complete before the reads)
     constexpr bool merge = (V & kSchedMerge) != 0 && kMergeLegal<N> && !LOCAL;
+    constexpr bool wave_sync = merge && np2 == 64;
     auto layer_sync = [] {
-        if constexpr (merge) {
+        if constexpr (wave_sync) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -209,7 +210,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
         for (int i = t; i < np2; i += S::threads) sDt[(i % n1) * n1 + i / n1] = Dm[i];
         if constexpr (three)
             for (int i = t; i < np2; i += S::threads) sD[i] = Dm[i];
-        if constexpr (merge) __syncthreads();  // filled by the first wave, read by all
+        if constexpr (wave_sync) __syncthreads();  // filled by the first wave, read by all
     }
 
     // gather through Z: the (a,b) column of the element
@@ -387,7 +388,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
             // neighbours, then each row goes out as one run of atomic adds (the
             // indices come from the lanes' own map entries; a shared face's two
             // copies agree)
-            static_assert(epb == 4 && S::threads == 4 * np2, "one element per wave, four per workgroup");
+            static_assert(epb >= 2, "a merged tile holds two or more elements");
             constexpr int L = epb * N + 1;
             __shared__ T sy[n1][n1][L];
             __shared__ uint32_t sid[n1][n1][L];
@@ -400,7 +401,7 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
                 }
             }
             __syncthreads();
-            if (a == N && el < last) {
+            if (active && a == N && el < last) {
 #pragma unroll
                 for (int c = 0; c < n1; ++c) sy[c][b][N * el + N] += yv[c];
             }
@@ -666,11 +667,11 @@ hb_status launch_ax_local_n(const hb_mesh_s *m, double lambda, const double *x, 
 }
 
 template <int N, bool MASK>
-hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int nitems, const BatchProb *probs,
-                            hipStream_t s)
+hb_status launch_batch_ax_n(int sched, const void *D, bool fp32, const WorkItem *items, int nitems,
+                            const BatchProb *probs, hipStream_t s)
 {
     if (nitems == 0) return HB_OK;
-    return with_schedule<N>(ax_schedule(N, fp32), [&](auto VV) -> hb_status {
+    return with_schedule<N>(sched, [&](auto VV) -> hb_status {
         constexpr int V = decltype(VV)::value;
         if (fp32)
             batch_ax_kernel<N, float, V, MASK><<<nitems, AxShape<N, V>::threads, 0, s>>>(items, probs,
@@ -700,10 +701,10 @@ hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int
     {                                                                                                          \
         return launch_ax_n<n, float, false>(m, m->geo32, m->D32, l, x, y, p, st, s);                           \
     }                                                                                                          \
-    hb_status launch_batch_ax_##n(const void *D, bool fp32, const WorkItem *it, int ni, const BatchProb *pr,   \
-                                  hipStream_t s)                                                               \
+    hb_status launch_batch_ax_##n(int v, const void *D, bool fp32, const WorkItem *it, int ni,                 \
+                                  const BatchProb *pr, hipStream_t s)                                          \
     {                                                                                                          \
-        return launch_batch_ax_n<n, false>(D, fp32, it, ni, pr, s);                                            \
+        return launch_batch_ax_n<n, false>(v, D, fp32, it, ni, pr, s);                                         \
     }                                                                                                          \
     int ax_epb_##n(int v) { return ax_epb_sched<n>(v); }                                                       \
     TileWalk ax_walk_##n(int64_t nx, int64_t ny, int64_t nz, int v) { return ax_walk_sched<n>(nx, ny, nz, v); }\
@@ -723,10 +724,10 @@ hb_status launch_batch_ax_n(const void *D, bool fp32, const WorkItem *items, int
     {                                                                                                          \
         return launch_ax_n<n, float, true>(m, m->geo32, m->D32, l, x, y, p, st, s);                            \
     }                                                                                                          \
-    hb_status launch_batch_ax_d_##n(const void *D, bool fp32, const WorkItem *it, int ni, const BatchProb *pr, \
-                                    hipStream_t s)                                                             \
+    hb_status launch_batch_ax_d_##n(int v, const void *D, bool fp32, const WorkItem *it, int ni,               \
+                                    const BatchProb *pr, hipStream_t s)                                        \
     {                                                                                                          \
-        return launch_batch_ax_n<n, true>(D, fp32, it, ni, pr, s);                                             \
+        return launch_batch_ax_n<n, true>(v, D, fp32, it, ni, pr, s);                                          \
     }                                                                                                          \
     }
 

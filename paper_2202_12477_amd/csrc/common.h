@@ -220,9 +220,15 @@ hb_status tune_class_cached(int N, bool fp32, int64_t local_nodes, hipStream_t s
 // the class's entry is the built-in default (no hb_set_schedule or autotuning
 // for it yet), launches of fewer than kSmallLaunch workgroups where an element
 // fits a wave take its one-wave form (the small configuration: 13.4 us per CG
-// iteration against 14.5 us).  ax_blocks counts the workgroups of this one.
+// iteration against 14.5 us).  Likewise a default merged schedule whose padded
+// rows would leave more than 15% of the tile slots empty (rows of few elements)
+// runs unmerged.  ax_blocks counts the workgroups of the one chosen.
 constexpr int kSmallLaunch = 256;
+constexpr double kMergeFill = 0.85;
 int mesh_schedule(const hb_mesh_s *m, bool fp32);
+// v without its merge bit where `elements` fill less than kMergeFill of the
+// slots of `tiles` merged tiles and the class's schedule is the built-in default.
+int unmerged_if_sparse(int N, bool fp32, int v, int64_t elements, int64_t tiles);
 // Schedule table (per degree and precision), shared by every solve path.
 int ax_schedule(int N, bool fp32);
 bool ax_schedule_legal(int N, int sched);
@@ -273,10 +279,11 @@ hb_status launch_round_f32(const double *in, float *out, int64_t n, hipStream_t 
 // Batched kernels (batch.hip).  Vector chunks hold kBatchChunk entries (four per
 // thread: 4096-entry chunks ran the 64-problem batch 6% slower).
 constexpr int kBatchChunk = 1024;
+// sched: the class's tile schedule (the one its work list was built for);
 // D: the degree's derivative matrix (FP32 copy when fp32), shared by the class;
 // dirichlet: the class's problems are Dirichlet boxes.
-hb_status launch_batch_ax(int N, const void *D, bool fp32, bool dirichlet, const WorkItem *items, int nitems,
-                          const BatchProb *probs, hipStream_t s);
+hb_status launch_batch_ax(int N, int sched, const void *D, bool fp32, bool dirichlet, const WorkItem *items,
+                          int nitems, const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_alpha(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_residual(const WorkItem *items, int nitems, const BatchProb *probs, hipStream_t s);
 hb_status launch_batch_beta(const int32_t *plist, int np, const BatchProb *probs, hipStream_t s);

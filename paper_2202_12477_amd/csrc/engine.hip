@@ -211,7 +211,7 @@ class BatchRunner {
         int mult, count;
     };
     struct Class {
-        int N;
+        int N, sched;
         bool fp32, dirichlet;
         int off;
         const void *D;              // the class's derivative matrix (any of its meshes)
@@ -347,7 +347,7 @@ class BatchRunner {
             const int need = static_cast<int>(j / iters) + 1;  // multiplier a problem needs to run sub-iteration j
             for (const Class &c : classes_) {
                 const int n = count_at(c.levels, need);
-                if (n > 0 && (st = launch_batch_ax(c.N, c.D, c.fp32, c.dirichlet, items_ + c.off, n, probs_, s)))
+                if (n > 0 && (st = launch_batch_ax(c.N, c.sched, c.D, c.fp32, c.dirichlet, items_ + c.off, n, probs_, s)))
                     return st;
             }
             const int nrun = count_at(run_levels_, need), nvec = count_at(vec_levels_, need);
@@ -481,11 +481,25 @@ class BatchRunner {
         HB_HIP(hipStreamSynchronize(s_));
         built_epoch_ = ax_schedule_epoch();  // read before the schedules themselves
         ++lists_version_;
-        // operator tiles under the current schedule of each problem's class
-        // (sets the list lengths, so before sizing the lists)
+        // each class's schedule: the table's, unmerged where its problems' rows
+        // leave the merged tiles sparse
+        int sched[kMaxN + 1][2];
+        int64_t elems[kMaxN + 1][2] = {}, tiles[kMaxN + 1][2] = {};
+        for (int N = 1; N <= kMaxN; ++N)
+            for (int f = 0; f < 2; ++f) sched[N][f] = ax_schedule(N, f != 0);
+        for (int i : run) {
+            const BatchProb &P = h_probs_[i];
+            const int f = P.use32 != 0;
+            elems[P.N][f] += P.E;
+            tiles[P.N][f] += ax_grid_for(P.N, P.E, P.nx, P.ny, P.nz, sched[P.N][f]);
+        }
+        for (int N = 1; N <= kMaxN; ++N)
+            for (int f = 0; f < 2; ++f) sched[N][f] = unmerged_if_sparse(N, f != 0, sched[N][f], elems[N][f], tiles[N][f]);
+        // operator tiles under the schedule of each problem's class (sets the
+        // list lengths, so before sizing the lists)
         for (int i : run) {
             BatchProb &P = h_probs_[i];
-            P.ax_tiles = ax_grid_for(P.N, P.E, P.nx, P.ny, P.nz, ax_schedule(P.N, P.use32 != 0));
+            P.ax_tiles = ax_grid_for(P.N, P.E, P.nx, P.ny, P.nz, sched[P.N][P.use32 != 0]);
         }
         size_t need = 0;
         for (int i : run) need += h_probs_[i].ax_tiles + h_probs_[i].vec_chunks;
@@ -512,13 +526,13 @@ class BatchRunner {
         for (int N = 1; N <= kMaxN; ++N)
             for (int k = 0; k < 4; ++k) {
                 const int f = k & 1, dir = k >> 1;
-                Class c{N, f != 0, dir != 0, nit, nullptr, {}};
+                Class c{N, sched[N][f], f != 0, dir != 0, nit, nullptr, {}};
                 for (int i : run) {
                     const BatchProb &P = h_probs_[i];
                     if (P.N != N || P.use32 != f || P.dirichlet != dir) continue;
                     c.D = f ? static_cast<const void *>(P.D32) : static_cast<const void *>(P.D);
                     // the single-problem launch's tile order (locality of the shared lines)
-                    const TileWalk w = ax_walk_for(P.N, P.nx, P.ny, P.nz, ax_schedule(P.N, f != 0));
+                    const TileWalk w = ax_walk_for(P.N, P.nx, P.ny, P.nz, c.sched);
                     for (int t = 0; t < P.ax_tiles; ++t)
                         h_items_[nit++] = WorkItem{i, static_cast<int32_t>(walk_tile(w, static_cast<uint32_t>(t)))};
                     c.levels.push_back(Level{mult_[i], nit - c.off});

@@ -139,8 +139,8 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
     # measured defaults (autotuner at 2^24 local nodes)
-    fp64 = [1, 1, 1, 3, 1, 0, 9, 0, 21, 0, 21, 21, 5, 5, 5]
-    fp32 = [0, 1, 0, 1, 1, 1, 8, 5, 0, 1, 21, 0, 21, 5, 4]
+    fp64 = [1, 1, 9, 3, 1, 8, 9, 8, 21, 8, 21, 21, 5, 5, 5]
+    fp32 = [8, 1, 8, 1, 9, 9, 8, 9, 9, 9, 21, 0, 21, 5, 4]
     for N in range(1, 16):
         assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
         assert hb.get_schedule(N, hb.PREC_FP32_RR) == fp32[N - 1]
@@ -151,10 +151,18 @@ def test_schedule_table_validation(L):
     assert hb.get_schedule(8, hb.PREC_FP64) == 5
     hb.set_schedule(8, hb.PREC_FP64, before8)
     assert L.hb_set_schedule(7, 0, hb.SCHED_LEAN) == hb.HB_ERR_INVALID_ARG  # lean registers: N >= 8 only
-    # merged assembly: N = 7 only (an element is one wave), not with one-wave workgroups
-    assert L.hb_set_schedule(8, 0, hb.SCHED_MERGE) == hb.HB_ERR_INVALID_ARG
-    assert L.hb_set_schedule(3, 0, hb.SCHED_MERGE) == hb.HB_ERR_INVALID_ARG
+    # merged assembly: N <= 10 (two or more elements per 256-thread tile), not with
+    # one-wave workgroups, the lean schedule or its three-wave form
+    assert L.hb_set_schedule(11, 0, hb.SCHED_MERGE) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(7, 0, hb.SCHED_MERGE | hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(3, 0, hb.SCHED_MERGE | hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(9, 0, hb.SCHED_MERGE | hb.SCHED_LEAN) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(9, 0, hb.SCHED_MERGE | 21) == hb.HB_ERR_INVALID_ARG
+    for N in (1, 3, 8, 10):
+        before = hb.get_schedule(N, hb.PREC_FP64)
+        hb.set_schedule(N, hb.PREC_FP64, hb.SCHED_MERGE | hb.SCHED_COLS_LDS)
+        assert hb.get_schedule(N, hb.PREC_FP64) == 9
+        hb.set_schedule(N, hb.PREC_FP64, before)
     # the three-wave form: N >= 8, with the lean schedule and D^T in LDS only
     assert L.hb_set_schedule(7, 0, 16) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(7, 0, 16 | 5) == hb.HB_ERR_INVALID_ARG

@@ -37,9 +37,8 @@ def say(msg):
 
 
 def legal(N):
-    if N == 7:
-        return {0, 1, 2, 3, 8, 9}
-    return {0, 1, 2, 3} if (N + 1) ** 2 <= 64 else {0, 1, 4, 5, 21}
+    base = {0, 1, 2, 3} if (N + 1) ** 2 <= 64 else {0, 1, 4, 5}
+    return base | ({8, 9} if (N + 1) ** 2 <= 128 else set()) | ({21} if N >= 8 else set())
 
 
 @pytest.fixture(autouse=True)

@@ -41,7 +41,8 @@ def relerr(a, b):
 
 
 def legal(N):
-    return [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5, 21]
+    base = [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5]
+    return base + ([8, 9] if (N + 1) ** 2 <= 128 else []) + ([21] if N >= 8 else [])
 
 
 @pytest.fixture(autouse=True)
