@@ -373,8 +373,11 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 /* Schedule values are 0..31.  While a class's entry is the built-in default */
 /* (neither set nor autotuned), a single-problem launch of fewer than 256    */
 /* workgroups (a tiny mesh) uses the one-wave form of that schedule where    */
-/* an element fits a wave.  The choice changes the reduction grouping of     */
-/* p.Ap, the order of assembly atomics and of the t-part sums only (results  */
+/* an element fits a wave, and a merged schedule (bit 3) runs without bit 3  */
+/* where its padded rows would fill less than 85% of the tile slots (per     */
+/* mesh; per class over the running problems in batched solves).  The       */
+/* choice changes the reduction grouping of p.Ap, the order of assembly      */
+/* atomics and of the t-part sums only (results                              */
 /* agree to rounding).  The table is process-wide, starts from measured      */
 /* defaults, and must not be changed while solves are in flight.  `prec`:    */
 /* HB_PREC_FP64 selects the FP64 operator's entry, either mixed precision    */
