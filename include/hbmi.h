@@ -361,13 +361,14 @@ hb_status hb_engine_poll(hb_engine engine, uint64_t ticket, int32_t *done, doubl
 /* columns of D for the divergence from LDS instead of registers; bit 1 (2)  */
 /* uses one-wave workgroups instead of 256-thread workgroups (N <= 7, where  */
 /* an element fits in a wave); bit 2 (4) keeps no f_t array and targets two  */
-/* waves per SIMD (N >= 8); bit 3 (8, N <= 10, not with bits 1, 2 or 4)     */
-/* makes the k elements of a 256-thread workgroup x-consecutive (k = 4 at   */
+/* waves per SIMD (N >= 8); bit 3 (8, N <= 10, not with bit 1; with bits 2  */
+/* and 4 only as 29, the merged three-wave form, N = 8-10) makes the k       */
+/* elements of a 256-thread workgroup x-consecutive (k = 4 at               */
 /* N = 7), sums their shared faces in LDS and assembles each row of kN+1    */
 /* DOFs once (where k does not divide nx, each row of the box ends in a     */
 /* shorter tile);                                                           */
-/* bit 4 (16, N >= 8, only with bits 0 and 2, i.e. value 21) also reads the  */
-/* rows of D from LDS, keeps the map column in LDS between gather and        */
+/* bit 4 (16, N >= 8, only with bits 0 and 2: value 21, or 29) also reads   */
+/* the rows of D from LDS, keeps the map column in LDS between gather and    */
 /* assembly, prefetches one geometry layer instead of two (FP64) and targets */
 /* three waves per SIMD.                                                     */
 /* Schedule values are 0..31.  While a class's entry is the built-in default */

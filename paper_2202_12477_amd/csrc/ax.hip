@@ -37,7 +37,7 @@ namespace {
 // size), kept where the winner beat the plain schedule by more than ~1.5%.
 constexpr int kDefaultSched[2][kMaxN + 1] = {
     // N: 0  1  2  3  4  5  6  7  8  9 10 11 12 13 14 15
-    {0, 1, 1, 9, 3, 1, 8, 9, 8, 21, 8, 21, 21, 5, 5, 5},  // FP64
+    {0, 1, 1, 9, 3, 1, 8, 9, 8, 29, 8, 21, 21, 5, 5, 5},  // FP64
     {0, 8, 1, 8, 1, 9, 9, 8, 9, 9, 9, 21, 0, 21, 5, 4},   // FP32
 };
 
@@ -68,8 +68,12 @@ bool ax_schedule_legal(int N, int v)
     const bool small = (N + 1) * (N + 1) <= 64;   // an element fits in a wave
     const bool merge = (N + 1) * (N + 1) <= 128;  // a 256-thread tile holds two or more elements
     const int lean_cols = kSchedLean | kSchedColsLds;
+    // merging goes with the 256-thread schedules and with the full three-wave form (29) only
+    const int rest = v & ~kSchedMerge;
+    const bool merge_ok = merge && !(v & kSchedWave) &&
+                          (!(v & (kSchedLean | kSchedThree)) || rest == (lean_cols | kSchedThree));
     return N >= 1 && N <= kMaxN && v >= 0 && v < kNumSched && (!(v & kSchedWave) || small) &&
-           (!(v & kSchedLean) || !small) && (!(v & kSchedMerge) || (merge && !(v & (kSchedWave | kSchedLean | kSchedThree)))) &&
+           (!(v & kSchedLean) || !small) && (!(v & kSchedMerge) || merge_ok) &&
            (!(v & kSchedThree) || (v & lean_cols) == lean_cols);
 }
 

@@ -397,7 +397,9 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
 #pragma unroll
                 for (int c = 0; c < n1; ++c) {
                     sy[c][b][N * el + a] = yv[c];
-                    sid[c][b][N * el + a] = idx[c];
+                    uint32_t id = idx[c];
+                    if constexpr (three) id = sidx[el * np3 + c * np2 + ab];  // parked in LDS
+                    sid[c][b][N * el + a] = id;
                 }
             }
             __syncthreads();
@@ -604,6 +606,7 @@ decltype(auto) with_schedule(int v, F &&f)
     case 8: return f(std::integral_constant<int, legal_sched<N>(8)>{});
     case 9: return f(std::integral_constant<int, legal_sched<N>(9)>{});
     case 21: return f(std::integral_constant<int, legal_sched<N>(21)>{});
+    case 29: return f(std::integral_constant<int, legal_sched<N>(29)>{});
     default: return f(std::integral_constant<int, 0>{});
     }
 }

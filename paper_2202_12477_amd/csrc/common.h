@@ -16,8 +16,9 @@ namespace hb {
 constexpr int kMaxN = 15;
 // Operator tile schedules (bit flags): D^T read from LDS; one-wave workgroups
 // (N <= 7); lean registers with two waves per SIMD (N >= 8); assembly of four
-// x-consecutive elements merged in LDS (N = 7: an element is one wave); the
-// three-wave form of the lean schedule with D^T in LDS (N >= 8, with both).
+// x-consecutive elements merged in LDS (N <= 10; at N = 7 an element is one
+// wave); the three-wave form of the lean schedule with D^T in LDS (N >= 8,
+// with both; merged too as 29 at N = 8-10).
 constexpr int kSchedColsLds = 1, kSchedWave = 2, kSchedLean = 4, kSchedMerge = 8, kSchedThree = 16,
               kNumSched = 32;
 constexpr int kGeo = 7;  // G_rr, G_rs, G_rt, G_ss, G_st, G_tt, c

@@ -139,7 +139,7 @@ def test_schedule_table_validation(L):
     assert L.hb_get_schedule(7, 9, ctypes.byref(v)) == hb.HB_ERR_INVALID_ARG
     assert L.hb_get_schedule(7, 0, None) == hb.HB_ERR_INVALID_ARG
     # measured defaults (autotuner at 2^24 local nodes)
-    fp64 = [1, 1, 9, 3, 1, 8, 9, 8, 21, 8, 21, 21, 5, 5, 5]
+    fp64 = [1, 1, 9, 3, 1, 8, 9, 8, 29, 8, 21, 21, 5, 5, 5]
     fp32 = [8, 1, 8, 1, 9, 9, 8, 9, 9, 9, 21, 0, 21, 5, 4]
     for N in range(1, 16):
         assert hb.get_schedule(N, hb.PREC_FP64) == fp64[N - 1]
@@ -157,7 +157,12 @@ def test_schedule_table_validation(L):
     assert L.hb_set_schedule(7, 0, hb.SCHED_MERGE | hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(3, 0, hb.SCHED_MERGE | hb.SCHED_WAVE) == hb.HB_ERR_INVALID_ARG
     assert L.hb_set_schedule(9, 0, hb.SCHED_MERGE | hb.SCHED_LEAN) == hb.HB_ERR_INVALID_ARG
-    assert L.hb_set_schedule(9, 0, hb.SCHED_MERGE | 21) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(9, 0, hb.SCHED_MERGE | hb.SCHED_LEAN | hb.SCHED_COLS_LDS) == hb.HB_ERR_INVALID_ARG
+    assert L.hb_set_schedule(11, 0, hb.SCHED_MERGE | 21) == hb.HB_ERR_INVALID_ARG
+    before9 = hb.get_schedule(9, hb.PREC_FP64)
+    hb.set_schedule(9, hb.PREC_FP64, hb.SCHED_MERGE | 21)  # merged three-wave form: N = 8-10
+    assert hb.get_schedule(9, hb.PREC_FP64) == 29
+    hb.set_schedule(9, hb.PREC_FP64, before9)
     for N in (1, 3, 8, 10):
         before = hb.get_schedule(N, hb.PREC_FP64)
         hb.set_schedule(N, hb.PREC_FP64, hb.SCHED_MERGE | hb.SCHED_COLS_LDS)

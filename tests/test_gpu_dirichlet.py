@@ -42,7 +42,7 @@ def relerr(a, b):
 
 def legal(N):
     base = [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5]
-    return base + ([8, 9] if (N + 1) ** 2 <= 128 else []) + ([21] if N >= 8 else [])
+    return base + ([8, 9] if (N + 1) ** 2 <= 128 else []) + ([21] if N >= 8 else []) + ([29] if 8 <= N <= 10 else [])
 
 
 @pytest.fixture(autouse=True)

@@ -46,7 +46,8 @@ def legal(N):
     base = [0, 1, 2, 3] if (N + 1) ** 2 <= 64 else [0, 1, 4, 5]
     merged = [8, 9] if (N + 1) ** 2 <= 128 else []
     three = [21] if N >= 8 else []
-    return base + merged + three
+    merged_three = [29] if 8 <= N <= 10 else []
+    return base + merged + three + merged_three
 
 
 @pytest.fixture(autouse=True)
@@ -122,7 +123,7 @@ def test_merged_assembly_matches_oracle(nx, ny, nz, dirichlet):
     m.close()
 
 
-@pytest.mark.parametrize("N,dirichlet", [(7, False), (7, True), (3, False), (6, True), (9, False), (10, False)])
+@pytest.mark.parametrize("N,dirichlet", [(7, False), (7, True), (3, False), (6, True), (9, False), (10, True)])
 def test_merged_cg_and_batch_match_default(N, dirichlet):
     """The fused p.Ap partials and the batched kernel under the merged schedule:
     fixed CG iterations agree with an unmerged schedule to rounding (25 below
@@ -155,7 +156,7 @@ def test_merged_cg_and_batch_match_default(N, dirichlet):
 
     hb.set_schedule(N, hb.PREC_FP64, 3 if (N + 1) ** 2 <= 64 else 1)
     x0 = run()
-    for v in (hb.SCHED_MERGE, hb.SCHED_MERGE | hb.SCHED_COLS_LDS):
+    for v in (hb.SCHED_MERGE, hb.SCHED_MERGE | hb.SCHED_COLS_LDS) + ((29,) if N >= 8 else ()):
         hb.set_schedule(N, hb.PREC_FP64, v)
         x1 = run()
         for k, (a, b) in enumerate(zip(x0, x1)):
