@@ -192,8 +192,9 @@ __device__ __attribute__((always_inline)) inline double ax_tile(TileSpan sp, gpt
             DbT[m] = Dm[m * n1 + b];
         }
     }
-    // merged assembly: each wave holds one element and its own LDS slices, so the
-    // layer loop synchronises within the wave (LDS writes complete before the reads)
+    // merged assembly at N = 7: each wave holds one element and its own LDS slices,
+    // so the layer loop synchronises within the wave (LDS writes complete before
+    // the reads); at the other degrees elements share waves and the workgroup syncs
     constexpr bool merge = (V & kSchedMerge) != 0 && kMergeLegal<N> && !LOCAL;
     constexpr bool wave_sync = merge && np2 == 64;
     auto layer_sync = [] {
